@@ -1,0 +1,62 @@
+"""Plants plausible mistakes in copies of the oracle's C source (on the CPU) and
+checks that the pins catch every one of them.  Each mutated build runs in its own
+process, so a mistake that corrupts memory cannot take the test runner down."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+import oracle
+
+MUTATIONS = {
+    "drop_last_key": ("j <= ORACLE_KEYS", "j < ORACLE_KEYS"),
+    "drop_first_key": ("for (int j = 1; j <= ORACLE_KEYS", "for (int j = 2; j <= ORACLE_KEYS"),
+    "no_abs": ("sum += (c < 0) ? -c : c;", "sum += c;"),
+    "same_operand": ("key_value(a, j) - key_value(b, j)", "key_value(a, j) - key_value(a, j)"),
+    "wrong_word": ("rec[j >> 6] >> (j & 63)", "rec[j >> 7] >> (j & 63)"),
+    "ties_descending": ("(d0 == d1 && i0 < i1)", "(d0 == d1 && i0 > i1)"),
+    "ties_ignored": ("d0 < d1 || (d0 == d1 && i0 < i1)", "d0 < d1"),
+    "keep_largest": ("return d0 < d1 ||", "return d0 > d1 ||"),
+    "k_minus_one": ("uint64_t want = k < total ? k : total;",
+                    "uint64_t want = k < total ? (k ? k - 1 : 0) : total;"),
+    "merge_drops_chunk": ("for (int j = 0; j < njobs; ++j)\n      for",
+                          "for (int j = 1; j < njobs; ++j)\n      for"),
+    "range_end_skipped": ("for (uint64_t i = begin[r]; i < end[r]; ++i)\n      topk_offer",
+                          "for (uint64_t i = begin[r]; i + 1 < end[r]; ++i)\n      topk_offer"),
+}
+
+RUNNER = r"""
+import json, sys
+sys.path.insert(0, sys.argv[2]); sys.path.insert(0, sys.argv[3])
+import oracle
+from pins import ALL_PINS
+orc = oracle.Oracle(sys.argv[1])
+failed = []
+for pin in ALL_PINS:
+    try:
+        pin(orc)
+    except AssertionError:
+        failed.append(pin.__name__)
+    print(json.dumps({"pin": pin.__name__, "failed": failed}), flush=True)
+"""
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_catch_mutation(name, tmp_path):
+    old, new = MUTATIONS[name]
+    src = open(oracle.SOURCE).read()
+    assert src.count(old) >= 1, f"mutation anchor for {name} not found"
+    cpath = os.path.join(tmp_path, "oracle_mut.c")
+    with open(cpath, "w") as f:
+        f.write(src.replace(old, new, 1))
+    so = oracle.compile_source(cpath, os.path.join(tmp_path, "oracle_mut.so"))
+    here = os.path.dirname(os.path.abspath(__file__))
+    root = os.path.dirname(here)
+    p = subprocess.run([sys.executable, "-c", RUNNER, so, here, root], capture_output=True,
+                       text=True, timeout=600)
+    lines = [json.loads(x) for x in p.stdout.splitlines() if x.startswith("{")]
+    failed = lines[-1]["failed"] if lines else []
+    crashed = p.returncode != 0
+    assert failed or crashed, f"no pin catches the planted mistake {name}"
