@@ -1,0 +1,267 @@
+/*
+ * fps.h -- C ABI of the MI355X exact fingerprint top-k engine.
+ *
+ * The engine answers the question of FPScreen (arXiv 1906.06170), Fig. 3: given a
+ * target MACCS-166 fingerprint and a library of fingerprints, return the N
+ * library entries with the smallest Manhattan distance to the target, with
+ * their distances, in ascending order.  The distance is the one of Section 4.3,
+ *     dist(a, b) = sum_{j=1..166} |a_j - b_j|,
+ * which for 0/1 keys equals the number of keys in which a and b differ.  Equal
+ * distances are ordered by ascending library index (the paper states no tie
+ * rule; this one makes the answer unique).  The library may be cut into strides
+ * (Section 2.1, Fig. 1); a query may search any union of strides and the
+ * results are combined into one global order (Section 4.3).
+ *
+ * Fingerprint layout (records and queries): three uint64 words; key j (1..166)
+ * is bit (j & 63) of word (j >> 6).  Bit 0 of word 0 and bits 39..63 of word 2
+ * (keys 167..191) must be zero: a record or query with any of them set is
+ * rejected with FPS_E_FINGERPRINT, never silently masked.
+ *
+ * Conventions for every call:
+ *   - the return value is an fps_status; FPS_OK is 0 and errors are negative;
+ *     nothing throws across this interface;
+ *   - fps_last_error() returns a message for the last failure on the calling
+ *     thread (empty string if none); the pointer stays valid until the next
+ *     call on that thread;
+ *   - all arguments are validated before any device work is queued;
+ *   - device memory is owned by the caller (typically torch tensors): the
+ *     library buffer and every workspace; the library handle owns only host
+ *     state, pinned host staging buffers and its device-side parameter cache;
+ *   - "stream" is a hipStream_t (NULL = the default stream); calls that return
+ *     results are synchronous with respect to that stream: they return after
+ *     the results are in host memory;
+ *   - one handle must not be used by two threads at once; concurrency between
+ *     requests comes from the server API below.
+ */
+#ifndef FPS_H
+#define FPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FPS_OK = 0,
+  FPS_E_ARG = -1,         /* NULL pointer, bad mask, bad size, buffer too small */
+  FPS_E_FINGERPRINT = -2, /* bit 0 or a bit above key 166 set in a record/query */
+  FPS_E_NOMEM = -3,       /* workspace smaller than fps_workspace_bytes, or host allocation failed */
+  FPS_E_DEVICE = -4,      /* a HIP runtime error (message from hipGetErrorString) */
+  FPS_E_STATE = -5,       /* handle used in a state that does not allow the call */
+  FPS_E_BUSY = -6         /* server admission full (non-blocking submit only) */
+} fps_status;
+
+#define FPS_KEYS 166
+#define FPS_WORDS 3
+#define FPS_MAX_STRIDES 32
+/* Stride mask selecting every stride of the library. */
+#define FPS_MASK_ALL 0xFFFFFFFFu
+
+typedef struct fps_library fps_library; /* opaque handle */
+
+/* One result: global library row and its distance (0..166). */
+typedef struct {
+  uint32_t index;
+  uint32_t distance;
+} fps_hit;
+
+/* Scan kernels a batch may use. */
+typedef enum {
+  FPS_PATH_AUTO = 0,     /* autotuner's choice (timed on first use per batch shape) */
+  FPS_PATH_SINGLE = 1,   /* the single-query scan, one query per pass over the library */
+  FPS_PATH_POPCOUNT = 2, /* batched XOR + popcount kernel */
+  FPS_PATH_MFMA_I8 = 3,  /* batched int8 matrix-core kernel (a.b with exact int32 sums) */
+  FPS_PATH_MFMA_F4 = 4   /* batched 4-bit-float matrix-core kernel (exact fp32 sums) */
+} fps_path;
+
+/* ------------------------------------------------------------------------ */
+/* Library (Fig. 3 step 1: the library file becomes the matrix A).           */
+/* ------------------------------------------------------------------------ */
+
+/* Device bytes needed to hold n records: 24 bytes per record, n rounded up to
+ * a multiple of 4096 (word-major layout: all first words, then all second
+ * words, then all third words). */
+size_t fps_library_device_bytes(uint64_t n);
+
+/*
+ * Validates n records and uploads them into device_buf in the engine's layout.
+ *   host_words:   n x 3 uint64, record-major, host memory (read only, not kept).
+ *   n:            1 <= n < 2^32.
+ *   stride_begin: nstrides + 1 non-decreasing offsets, stride_begin[0] = 0 and
+ *                 stride_begin[nstrides] = n; stride s holds records
+ *                 [stride_begin[s], stride_begin[s+1]).  NULL means one stride.
+ *   nstrides:     1..FPS_MAX_STRIDES (ignored when stride_begin is NULL).
+ *   device_buf:   caller-owned device memory of device_bytes >=
+ *                 fps_library_device_bytes(n); it must stay allocated and
+ *                 unmodified until fps_library_free.  Its contents are
+ *                 overwritten.
+ *   stream:       hipStream_t for the upload; the call returns after it ends.
+ *   out:          receives the handle.
+ * Errors: FPS_E_ARG (NULL, n out of range, bad strides, small buffer),
+ * FPS_E_FINGERPRINT (the message names the first bad row), FPS_E_DEVICE.
+ */
+fps_status fps_library_load(const uint64_t *host_words, uint64_t n, const uint64_t *stride_begin,
+                            uint32_t nstrides, void *device_buf, size_t device_bytes,
+                            void *stream, fps_library **out);
+
+/* Library size and stride table (stride_begin may be NULL; else nstrides+1 entries). */
+fps_status fps_library_info(const fps_library *lib, uint64_t *n, uint32_t *nstrides,
+                            uint64_t *stride_begin);
+
+/* Releases the handle and its host state.  Never frees device_buf. NULL is OK. */
+fps_status fps_library_free(fps_library *lib);
+
+/* Selects the batch scan kernel (default FPS_PATH_AUTO). */
+fps_status fps_set_path(fps_library *lib, fps_path path);
+
+/* ------------------------------------------------------------------------ */
+/* Search (Fig. 3 steps 2-6; single and batch searches of Section 4.4).       */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Device workspace bytes for a search of q queries with per-query k[] and
+ * stride masks mask[] (mask NULL = FPS_MASK_ALL for every query).  The same
+ * value is valid for fps_search (q = 1) and fps_search_batch.
+ * Errors: FPS_E_ARG (NULL lib/k/bytes, q == 0, a zero mask or a mask naming a
+ * stride the library does not have).
+ */
+fps_status fps_workspace_bytes(const fps_library *lib, uint32_t q, const uint32_t *k,
+                               const uint32_t *mask, size_t *bytes);
+
+/*
+ * One query (Fig. 3; the "single molecular search" of Section 4.4).
+ *   query:  3 uint64 words, host memory.
+ *   k:      number of results wanted (0 allowed).
+ *   mask:   strides to search (bit s = stride s) or FPS_MASK_ALL.
+ *   workspace/ws_bytes: caller-owned device memory, at least
+ *           fps_workspace_bytes(lib, 1, &k, &mask).
+ *   out:    host memory with room for min(k, n_eff) hits, n_eff being the number
+ *           of records in the selected strides; written in ascending
+ *           (distance, index) order.
+ *   n_out:  receives min(k, n_eff).
+ * Errors: FPS_E_ARG, FPS_E_FINGERPRINT, FPS_E_NOMEM, FPS_E_DEVICE.
+ */
+fps_status fps_search(fps_library *lib, const uint64_t query[3], uint32_t k, uint32_t mask,
+                      void *workspace, size_t ws_bytes, fps_hit *out, uint32_t *n_out,
+                      void *stream);
+
+/*
+ * Independent queries in one launch sequence (the batch search of Section 4.4
+ * without its clustering step).
+ *   queries:  q x 3 uint64, record-major, host memory.
+ *   k:        q result counts; mask: q stride masks or NULL (all strides).
+ *   out:      host memory of out_capacity hits; query i's hits are
+ *             out[out_offset[i] .. out_offset[i+1]), min(k[i], n_eff[i]) of them,
+ *             in ascending (distance, index) order.
+ *   out_offset: host array of q + 1 entries, filled by the call.
+ * Errors: FPS_E_ARG (also when out_capacity < sum of min(k[i], n_eff[i])),
+ * FPS_E_FINGERPRINT (the message names the first bad query), FPS_E_NOMEM,
+ * FPS_E_DEVICE.
+ */
+fps_status fps_search_batch(fps_library *lib, const uint64_t *queries, uint32_t q,
+                            const uint32_t *k, const uint32_t *mask, void *workspace,
+                            size_t ws_bytes, fps_hit *out, uint64_t out_capacity,
+                            uint64_t *out_offset, void *stream);
+
+/* Counters of the last search on this handle (for tests and benchmarks). */
+typedef struct {
+  uint32_t path;          /* fps_path actually used */
+  uint32_t queries;       /* queries in the call */
+  uint32_t fallbacks;     /* queries answered by the exact two-pass fallback */
+  uint32_t reserved;
+  uint64_t candidates;    /* candidates appended by the scan, summed over queries */
+  double scan_ms;         /* device time of the scan kernel(s) of the call */
+  double total_ms;        /* device time from the first to the last kernel */
+} fps_search_stats;
+
+fps_status fps_last_search_stats(const fps_library *lib, fps_search_stats *stats);
+
+/* ------------------------------------------------------------------------ */
+/* Tuning knobs, for tests that must force the rare paths.                   */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * candidate_scale: multiplies every query's candidate-buffer capacity (1.0 is
+ *   the default; tiny values force the overflow fallback).
+ * sample_records:  records per query used to derive the distance bound (0 =
+ *   default 2^20).
+ * force_fallback:  nonzero answers every query with the exact two-pass path.
+ * These change workspace sizes: query fps_workspace_bytes after setting them.
+ */
+fps_status fps_set_tuning(fps_library *lib, double candidate_scale, uint64_t sample_records,
+                          int force_fallback);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of independent requests (the queue between the */
+/* user side and the computing side, Sections 3.1 and 4.4).                    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct fps_server fps_server;
+
+typedef struct {
+  size_t pool_bytes;          /* device workspace pool the server may use (<= ws_bytes) */
+  uint32_t max_batch_queries; /* cap on queries coalesced into one batch */
+  uint32_t max_wait_us;       /* longest a request waits for others to join its batch */
+  uint32_t n_streams;         /* batches in flight at once (1..8) */
+  uint32_t reserved;
+} fps_server_config;
+
+typedef struct {
+  uint64_t submit_ns;   /* steady-clock times */
+  uint64_t start_ns;    /* batch launch */
+  uint64_t done_ns;     /* results available */
+  uint32_t batch_id;
+  uint32_t batch_queries;
+} fps_request_stats;
+
+typedef struct {
+  uint64_t requests;
+  uint64_t queries;
+  uint64_t batches;
+  uint64_t deadline_misses;
+  double p50_us, p99_us, max_us, mean_batch_queries;
+} fps_server_stats;
+
+/*
+ * Creates a server over a loaded library.  workspace/ws_bytes: caller-owned
+ * device memory, carved into n_streams slots.  The server owns one worker
+ * thread and n_streams HIP streams (default priority).
+ */
+fps_status fps_server_create(fps_library *lib, const fps_server_config *cfg, void *workspace,
+                             size_t ws_bytes, fps_server **out);
+
+/*
+ * Queues one request of q queries (host memory, copied before return) with one k
+ * and one stride mask.  deadline_us is the request's latency budget (counted as
+ * a miss when exceeded; the request still completes).  Blocks while the pool
+ * lacks room for the request unless nonblocking != 0, which returns
+ * FPS_E_BUSY instead.  A request larger than a whole slot is rejected with
+ * FPS_E_NOMEM.
+ */
+fps_status fps_server_submit(fps_server *srv, const uint64_t *queries, uint32_t q, uint32_t k,
+                             uint32_t mask, uint32_t deadline_us, int nonblocking,
+                             uint64_t *ticket);
+
+/*
+ * Waits for a request and copies its results: out has out_capacity hits,
+ * out_offset q + 1 entries (as fps_search_batch).  stats may be NULL.  Each
+ * ticket can be waited for once.
+ */
+fps_status fps_server_wait(fps_server *srv, uint64_t ticket, fps_hit *out, uint64_t out_capacity,
+                           uint64_t *out_offset, fps_request_stats *stats);
+
+/* Latency and throughput counters since creation (or the last reset). */
+fps_status fps_server_stats_get(fps_server *srv, fps_server_stats *stats, int reset);
+
+/* Drains outstanding requests and releases the server (never the workspace). */
+fps_status fps_server_destroy(fps_server *srv);
+
+/* Message of the last failure on the calling thread. */
+const char *fps_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FPS_H */

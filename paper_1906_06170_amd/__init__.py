@@ -1,0 +1,318 @@
+"""Python binding of libfps.so, the MI355X exact fingerprint top-k engine.
+
+Argument marshalling only: every step of a search runs in the HIP library
+(include/fps.h).  PyTorch supplies device memory (the library rows and the
+workspaces are torch tensors owned by the objects below) and the current HIP
+stream.  There is no CPU path: importing the binding without a built
+libfps.so raises, and so does using it without a GPU.
+
+The problem is the one of FPScreen (arXiv 1906.06170), Fig. 3: the N library
+records nearest to a MACCS-166 query under the Manhattan distance of Section
+4.3, ascending, ties by library index; searches may be restricted to strides
+of the library (Section 2.1) and merged globally (Section 4.3).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(_HERE, "libfps.so")
+
+FPS_OK, FPS_E_ARG, FPS_E_FINGERPRINT, FPS_E_NOMEM, FPS_E_DEVICE, FPS_E_STATE, FPS_E_BUSY = (
+    0, -1, -2, -3, -4, -5, -6)
+STATUS_NAMES = {0: "FPS_OK", -1: "FPS_E_ARG", -2: "FPS_E_FINGERPRINT", -3: "FPS_E_NOMEM",
+                -4: "FPS_E_DEVICE", -5: "FPS_E_STATE", -6: "FPS_E_BUSY"}
+MASK_ALL = 0xFFFFFFFF
+PATH_AUTO, PATH_SINGLE, PATH_POPCOUNT, PATH_MFMA_I8, PATH_MFMA_F4 = 0, 1, 2, 3, 4
+PATH_NAMES = {0: "auto", 1: "single", 2: "popcount", 3: "mfma_i8", 4: "mfma_f4"}
+
+HIT_DTYPE = np.dtype([("index", np.uint32), ("distance", np.uint32)])
+
+
+class FPSError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class SearchStats(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_uint32), ("queries", ctypes.c_uint32),
+                ("fallbacks", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("candidates", ctypes.c_uint64), ("scan_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("pool_bytes", ctypes.c_size_t), ("max_batch_queries", ctypes.c_uint32),
+                ("max_wait_us", ctypes.c_uint32), ("n_streams", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class RequestStats(ctypes.Structure):
+    _fields_ = [("submit_ns", ctypes.c_uint64), ("start_ns", ctypes.c_uint64),
+                ("done_ns", ctypes.c_uint64), ("batch_id", ctypes.c_uint32),
+                ("batch_queries", ctypes.c_uint32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("requests", ctypes.c_uint64), ("queries", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("deadline_misses", ctypes.c_uint64),
+                ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
+                ("max_us", ctypes.c_double), ("mean_batch_queries", ctypes.c_double)]
+
+
+EXPORTS = {
+    # name: (restype, argtypes)
+    "fps_library_device_bytes": (ctypes.c_size_t, [ctypes.c_uint64]),
+    "fps_library_load": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                        ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t,
+                                        ctypes.c_void_p, ctypes.c_void_p]),
+    "fps_library_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
+    "fps_library_free": (ctypes.c_int, [ctypes.c_void_p]),
+    "fps_set_path": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "fps_workspace_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p]),
+    "fps_search": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                  ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fps_search_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_size_t, ctypes.c_void_p, ctypes.c_uint64,
+                                        ctypes.c_void_p, ctypes.c_void_p]),
+    "fps_last_search_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "fps_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_uint64,
+                                      ctypes.c_int]),
+    "fps_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_size_t, ctypes.c_void_p]),
+    "fps_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                         ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                         ctypes.c_int, ctypes.c_void_p]),
+    "fps_server_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                       ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]),
+    "fps_server_stats_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "fps_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "fps_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load_library(path: str = SO_PATH):
+    """ctypes handle of libfps.so with argument types set.  Raises if not built."""
+    global _lib
+    if _lib is not None and path == SO_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path == SO_PATH:
+        _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != FPS_OK:
+        msg = load_library().fps_last_error()
+        raise FPSError(rc, msg.decode() if msg else "")
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _require_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the fingerprint engine needs a ROCm GPU; none is visible")
+    return torch
+
+
+def device_bytes(n: int) -> int:
+    return int(load_library().fps_library_device_bytes(n))
+
+
+def _u32(a, n, default=None) -> np.ndarray:
+    if a is None:
+        return np.full(n, default, dtype=np.uint32)
+    a = np.asarray(a)
+    if a.ndim == 0:
+        return np.full(n, int(a), dtype=np.uint32)
+    return np.ascontiguousarray(a, dtype=np.uint32)
+
+
+class Library:
+    """A fingerprint library resident in HBM (Fig. 3 step 1)."""
+
+    def __init__(self, words: np.ndarray, strides=None, stream=None):
+        torch = _require_gpu()
+        c = load_library()
+        w = np.ascontiguousarray(words, dtype=np.uint64).reshape(-1, 3)
+        self.n = int(w.shape[0])
+        nbytes = int(c.fps_library_device_bytes(self.n))
+        self._buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self._ws = None
+        self._handle = ctypes.c_void_p()
+        if strides is None:
+            st, ns = None, 0
+        else:
+            st = np.ascontiguousarray(strides, dtype=np.uint64)
+            ns = len(st) - 1
+        self.strides = [0, self.n] if strides is None else [int(x) for x in strides]
+        _check(c.fps_library_load(_ptr(w), self.n, None if st is None else _ptr(st), ns,
+                                  ctypes.c_void_p(self._buf.data_ptr()), nbytes, _stream(stream),
+                                  ctypes.byref(self._handle)))
+
+    # -- helpers --------------------------------------------------------------
+    @property
+    def handle(self):
+        return self._handle
+
+    def close(self):
+        if self._handle:
+            load_library().fps_library_free(self._handle)
+            self._handle = ctypes.c_void_p()
+        self._buf = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, k, mask=None, q: int | None = None) -> int:
+        k = np.atleast_1d(np.asarray(k))
+        q = len(k) if q is None else q
+        kk = _u32(k if len(k) == q else np.full(q, int(k[0])), q)
+        mm = None if mask is None else _u32(mask, q)
+        out = ctypes.c_size_t()
+        _check(load_library().fps_workspace_bytes(self._handle, q, _ptr(kk),
+                                                  None if mm is None else _ptr(mm),
+                                                  ctypes.byref(out)))
+        return int(out.value)
+
+    def _workspace(self, nbytes: int):
+        import torch
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = None
+            self._ws = torch.empty(max(nbytes, 1 << 20), dtype=torch.uint8, device="cuda")
+        return self._ws
+
+    def set_path(self, path: int):
+        _check(load_library().fps_set_path(self._handle, int(path)))
+
+    def set_tuning(self, candidate_scale: float = 1.0, sample_records: int = 0,
+                   force_fallback: bool = False):
+        _check(load_library().fps_set_tuning(self._handle, float(candidate_scale),
+                                             int(sample_records), int(bool(force_fallback))))
+
+    def last_stats(self) -> dict:
+        st = SearchStats()
+        _check(load_library().fps_last_search_stats(self._handle, ctypes.byref(st)))
+        return {"path": PATH_NAMES.get(st.path, st.path), "queries": st.queries,
+                "fallbacks": st.fallbacks, "candidates": st.candidates,
+                "scan_ms": st.scan_ms, "total_ms": st.total_ms}
+
+    # -- search ---------------------------------------------------------------
+    def search(self, query, k: int, mask: int = MASK_ALL, stream=None) -> np.ndarray:
+        """Top-k of one query: structured array (index, distance), ascending."""
+        q = np.ascontiguousarray(np.asarray(query, dtype=np.uint64).reshape(3))
+        kk = np.array([k], dtype=np.uint32)
+        mm = np.array([mask], dtype=np.uint32)
+        nb = ctypes.c_size_t()
+        _check(load_library().fps_workspace_bytes(self._handle, 1, _ptr(kk), _ptr(mm),
+                                                  ctypes.byref(nb)))
+        ws = self._workspace(int(nb.value))
+        out = np.empty(max(int(k), 1), dtype=HIT_DTYPE)
+        nout = ctypes.c_uint32()
+        _check(load_library().fps_search(self._handle, _ptr(q), int(k), int(mask),
+                                         ctypes.c_void_p(ws.data_ptr()), ws.numel(), _ptr(out),
+                                         ctypes.byref(nout), _stream(stream)))
+        return out[:nout.value].copy()
+
+    def search_batch(self, queries, k, mask=None, stream=None):
+        """Independent top-k per query.  Returns (hits, offsets): query i's hits
+        are hits[offsets[i]:offsets[i+1]]."""
+        qs = np.ascontiguousarray(np.asarray(queries, dtype=np.uint64).reshape(-1, 3))
+        nq = qs.shape[0]
+        kk = _u32(k, nq)
+        mm = None if mask is None else _u32(mask, nq)
+        nb = ctypes.c_size_t()
+        _check(load_library().fps_workspace_bytes(self._handle, nq, _ptr(kk),
+                                                  None if mm is None else _ptr(mm),
+                                                  ctypes.byref(nb)))
+        ws = self._workspace(int(nb.value))
+        cap = int(kk.astype(np.uint64).sum())
+        out = np.empty(max(cap, 1), dtype=HIT_DTYPE)
+        off = np.zeros(nq + 1, dtype=np.uint64)
+        _check(load_library().fps_search_batch(
+            self._handle, _ptr(qs), nq, _ptr(kk), None if mm is None else _ptr(mm),
+            ctypes.c_void_p(ws.data_ptr()), ws.numel(), _ptr(out), cap, _ptr(off),
+            _stream(stream)))
+        return out[:int(off[-1])].copy(), off
+
+
+class Server:
+    """Continuous-batching request loop over a Library (Sections 3.1, 4.4)."""
+
+    def __init__(self, library: Library, pool_bytes: int, max_batch_queries: int = 512,
+                 max_wait_us: int = 0, n_streams: int = 2):
+        torch = _require_gpu()
+        self._lib = library
+        self._ws = torch.empty(int(pool_bytes), dtype=torch.uint8, device="cuda")
+        cfg = ServerConfig(int(pool_bytes), int(max_batch_queries), int(max_wait_us),
+                           int(n_streams), 0)
+        self._h = ctypes.c_void_p()
+        _check(load_library().fps_server_create(library.handle, ctypes.byref(cfg),
+                                                ctypes.c_void_p(self._ws.data_ptr()),
+                                                int(pool_bytes), ctypes.byref(self._h)))
+
+    def submit(self, queries, k: int, mask: int = MASK_ALL, deadline_us: int = 0,
+               nonblocking: bool = False) -> int:
+        qs = np.ascontiguousarray(np.asarray(queries, dtype=np.uint64).reshape(-1, 3))
+        t = ctypes.c_uint64()
+        _check(load_library().fps_server_submit(self._h, _ptr(qs), qs.shape[0], int(k),
+                                                int(mask), int(deadline_us), int(nonblocking),
+                                                ctypes.byref(t)))
+        return int(t.value)
+
+    def wait(self, ticket: int, nq: int, k: int):
+        out = np.empty(max(nq * int(k), 1), dtype=HIT_DTYPE)
+        off = np.zeros(nq + 1, dtype=np.uint64)
+        st = RequestStats()
+        _check(load_library().fps_server_wait(self._h, int(ticket), _ptr(out), nq * int(k),
+                                              _ptr(off), ctypes.byref(st)))
+        stats = {"submit_ns": st.submit_ns, "start_ns": st.start_ns, "done_ns": st.done_ns,
+                 "batch_id": st.batch_id, "batch_queries": st.batch_queries}
+        return out[:int(off[-1])].copy(), off, stats
+
+    def stats(self, reset: bool = False) -> dict:
+        st = ServerStats()
+        _check(load_library().fps_server_stats_get(self._h, ctypes.byref(st), int(reset)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            load_library().fps_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,105 @@
+// Internal declarations of the MI355X fingerprint top-k engine: device-side
+// parameter blocks and the host launchers of the kernels.
+//
+// Library layout in HBM (word-major): w0[Np], w1[Np], w2[Np] (uint64), Np = n
+// rounded up to a multiple of 4096.  Key j (1..166) of record i is bit (j & 63)
+// of w{j >> 6}[i].  Records [n, Np) are zero and never reported.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/fps.h"
+
+namespace fps {
+
+constexpr int kKeys = 166;
+constexpr int kBins = 168;          // distances 0..166, padded
+constexpr uint64_t kRowAlign = 4096;
+constexpr uint32_t kSortCap = 8192; // candidates with d <= D_k sorted in LDS by one block
+constexpr int kFbBlocks = 2048;     // fallback grid (blocks of 256 threads)
+constexpr int kFbWaves = kFbBlocks * 4;
+
+// A union of record ranges (the strides one mask selects), in ascending order,
+// adjacent strides merged.  Virtual index v in [0, neff) enumerates its records
+// in ascending global order.
+struct RangeSet {
+  uint32_t nranges;
+  uint32_t mask;
+  uint64_t neff;
+  uint64_t begin[FPS_MAX_STRIDES];
+  uint64_t end[FPS_MAX_STRIDES];
+  uint64_t voff[FPS_MAX_STRIDES + 1];  // virtual index of begin[r]
+  uint64_t t1off[FPS_MAX_STRIDES + 1]; // first single-scan tile of range r (512-record tiles)
+  uint64_t tboff[FPS_MAX_STRIDES + 1]; // first batch tile of range r (kBatchTile records)
+};
+
+constexpr int kScanTile = 512;      // records per wave iteration of the single-query scan
+constexpr int kBatchTile = 2048;    // records per work item of the batched kernels
+
+// Per-query parameters, uploaded with every call.
+struct QueryInfo {
+  uint64_t w[3];
+  uint32_t keff;      // min(k, neff)
+  uint32_t rset;      // RangeSet index
+  uint64_t cand_off;  // first candidate slot
+  uint32_t cap;       // candidate slots
+  uint32_t popc;      // keys set in the query
+  uint64_t out_off;   // first output hit
+  uint64_t sample;    // records used for the bound: min(sample_records, neff)
+};
+
+// A block of queries sharing one RangeSet (indices into the permutation).
+struct QBlock {
+  uint32_t first;  // position in perm[]
+  uint32_t count;  // queries in the block
+  uint32_t rset;
+  uint32_t pad;
+};
+
+// Work item of the batched kernels: a query block x one tile of its RangeSet.
+// Items are enumerated implicitly: item = qb_item_off[qb] + tile.
+struct Workspace {
+  RangeSet *rsets;
+  QueryInfo *qinfo;
+  uint32_t *perm;
+  QBlock *qblocks;      // for the batched kernels
+  uint64_t *qb_item_off;// nqb + 1 prefix of work items
+  QBlock *bblocks;      // for the bound kernel (<= 32 queries each)
+  uint32_t *T;          // per-query distance bound
+  uint32_t *count;      // per-query candidates appended (exact even past cap)
+  uint32_t *flags;      // per-query: 1 overflow, 2 too many ties for LDS sort, 4 bound failed
+  uint32_t *hist;       // per-query kBins histogram of the bound sample
+  uint64_t *cand;       // candidates: (distance << 32) | index
+  fps_hit *out;         // results, query q at qinfo[q].out_off
+  uint32_t *fb_wave_hist; // fallback: kFbWaves x kBins
+  uint32_t *fb_wave_off;  // fallback: kFbWaves x kBins
+  uint32_t *fb_bin_total; // fallback: kBins
+};
+
+struct Lib {
+  const uint64_t *w0, *w1, *w2;
+  uint64_t n, np;
+};
+
+// ---- launchers (kernels.hip) ----
+void launch_prep(const Workspace &ws, uint32_t q, hipStream_t s);
+void launch_bound(const Lib &lib, const Workspace &ws, uint32_t nbblocks, uint64_t max_sample,
+                  hipStream_t s);
+void launch_threshold(const Workspace &ws, uint32_t q, hipStream_t s);
+void launch_scan_single(const Lib &lib, const Workspace &ws, uint32_t qidx, uint64_t tiles,
+                        int cus, hipStream_t s);
+void launch_scan_popcount(const Lib &lib, const Workspace &ws, uint32_t nqb, uint64_t items,
+                          int cus, hipStream_t s);
+void launch_select(const Workspace &ws, uint32_t q, hipStream_t s);
+void launch_fallback(const Lib &lib, const Workspace &ws, uint32_t qidx, uint64_t neff,
+                     hipStream_t s);
+// ---- launchers (mfma.hip) ----
+void launch_scan_mfma_i8(const Lib &lib, const Workspace &ws, uint32_t nqb, uint64_t items,
+                         int cus, hipStream_t s);
+
+constexpr int kPopQBlock = 128;   // queries per block of the popcount kernel
+constexpr int kMfmaQBlock = 256;  // queries per block of the int8 MFMA kernel
+constexpr int kBoundQBlock = 32;  // queries per block of the bound kernel
+
+}  // namespace fps

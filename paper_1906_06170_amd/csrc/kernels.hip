@@ -1,0 +1,491 @@
+// Scan, bound, select and fallback kernels for gfx950 (wave64).
+//
+// The search of FPScreen (Fig. 3) computes, for every library row, the
+// Manhattan distance of Section 4.3 to the query and keeps the N smallest.  On
+// 0/1 keys that distance is the number of differing keys, so one record costs
+// three XORs and six 32-bit popcounts.  Top-N is exact and single-pass over the
+// library:
+//   1. bound:  a histogram of the distances of the first S records of each
+//      query's range gives T = the k-th smallest of them, an upper bound of the
+//      k-th smallest over the whole range;
+//   2. scan:   every record with d <= T is appended to the query's candidate
+//      buffer (wave-aggregated: one atomic per wave that has hits);
+//   3. select: a 167-bin histogram of the candidates gives D_k; the candidates
+//      with d <= D_k are sorted by (d, index) in LDS and the first k are kept.
+// A query whose candidates overflow their buffer, or whose ties at D_k exceed
+// the LDS sort, is answered by an exact two-pass ordered fallback.
+#include "fps_internal.h"
+
+namespace fps {
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ uint32_t rank_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Global record index of virtual index v of a RangeSet.
+__device__ __forceinline__ uint64_t v2g(const RangeSet *rs, uint64_t v) {
+  uint32_t r = 0;
+  const uint32_t nr = rs->nranges;
+  while (r + 1 < nr && v >= rs->voff[r + 1]) ++r;
+  return rs->begin[r] + (v - rs->voff[r]);
+}
+
+__device__ __forceinline__ uint32_t dist3(uint64_t a, uint64_t b, uint64_t c, uint64_t q0,
+                                          uint64_t q1, uint64_t q2) {
+  return (uint32_t)(__popcll(a ^ q0) + __popcll(b ^ q1) + __popcll(c ^ q2));
+}
+
+// Appends key for every lane with hit set: one atomic per wave.
+__device__ __forceinline__ void wave_append(bool hit, uint64_t key, uint32_t *cnt, uint64_t *cand,
+                                            uint32_t cap) {
+  const uint64_t bal = __ballot(hit);
+  if (bal == 0) return;
+  const uint32_t lane = lane_id();
+  const uint32_t leader = (uint32_t)__ffsll((unsigned long long)bal) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(cnt, (uint32_t)__popcll(bal));
+  base = __shfl(base, (int)leader);
+  if (hit) {
+    const uint32_t pos = base + rank_below(bal);
+    if (pos < cap) cand[pos] = key;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Clears the per-query counters and histograms (a fill kernel, so the sequence
+// can be captured into a graph).
+// ---------------------------------------------------------------------------
+__global__ void k_prep(Workspace ws, uint32_t q) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < q; i += stride) {
+    ws.count[i] = 0;
+    ws.flags[i] = 0;
+    ws.T[i] = (uint32_t)kKeys;
+  }
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < q * kBins; i += stride)
+    ws.hist[i] = 0;
+}
+
+void launch_prep(const Workspace &ws, uint32_t q, hipStream_t s) {
+  uint32_t blocks = (q * kBins + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(256), 0, s, ws, q);
+}
+
+// ---------------------------------------------------------------------------
+// Bound: distance histogram of the first `sample` records of each query's
+// range.  Grid: x = sample chunk, y = block of <= 32 queries sharing a range.
+// ---------------------------------------------------------------------------
+constexpr int kBoundChunk = 8192;
+
+__global__ __launch_bounds__(256) void k_bound(Lib lib, Workspace ws) {
+  __shared__ uint32_t h[kBoundQBlock * kBins];
+  __shared__ uint64_t qw[kBoundQBlock][3];
+  const QBlock bb = ws.bblocks[blockIdx.y];
+  const RangeSet *rs = ws.rsets + bb.rset;
+  const uint64_t sample = ws.qinfo[ws.perm[bb.first]].sample;
+  const uint64_t v0 = (uint64_t)blockIdx.x * kBoundChunk;
+  if (v0 >= sample) return;  // whole block
+  const uint64_t v1 = min(v0 + (uint64_t)kBoundChunk, sample);
+  for (uint32_t i = threadIdx.x; i < bb.count * kBins; i += blockDim.x) h[i] = 0;
+  for (uint32_t i = threadIdx.x; i < bb.count * 3; i += blockDim.x)
+    qw[i / 3][i % 3] = ws.qinfo[ws.perm[bb.first + i / 3]].w[i % 3];
+  __syncthreads();
+  for (uint64_t v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
+    const uint64_t g = v2g(rs, v);
+    const uint64_t a = lib.w0[g], b = lib.w1[g], c = lib.w2[g];
+    for (uint32_t j = 0; j < bb.count; ++j) {
+      const uint32_t d = dist3(a, b, c, qw[j][0], qw[j][1], qw[j][2]);
+      atomicAdd(&h[j * kBins + d], 1u);
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < bb.count * kBins; i += blockDim.x) {
+    const uint32_t x = h[i];
+    if (x) atomicAdd(&ws.hist[(uint64_t)ws.perm[bb.first + i / kBins] * kBins + i % kBins], x);
+  }
+}
+
+void launch_bound(const Lib &lib, const Workspace &ws, uint32_t nbblocks, uint64_t max_sample,
+                  hipStream_t s) {
+  if (nbblocks == 0 || max_sample == 0) return;
+  const uint32_t chunks = (uint32_t)((max_sample + kBoundChunk - 1) / kBoundChunk);
+  hipLaunchKernelGGL(k_bound, dim3(chunks, nbblocks), dim3(256), 0, s, lib, ws);
+}
+
+// T = smallest t whose cumulative sample count reaches keff.  keff = 0 gives
+// T = -1 (no candidate can pass); a sample too small to hold keff records gives
+// T = 166 (every record passes).
+__global__ void k_threshold(Workspace ws, uint32_t q) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= q) return;
+  const uint32_t keff = ws.qinfo[i].keff;
+  uint32_t T = (uint32_t)kKeys;
+  if (keff == 0) {
+    T = 0xFFFFFFFFu;
+  } else {
+    uint64_t cum = 0;
+    for (uint32_t t = 0; t <= (uint32_t)kKeys; ++t) {
+      cum += ws.hist[(uint64_t)i * kBins + t];
+      if (cum >= keff) {
+        T = t;
+        break;
+      }
+    }
+  }
+  ws.T[i] = T;
+}
+
+void launch_threshold(const Workspace &ws, uint32_t q, hipStream_t s) {
+  hipLaunchKernelGGL(k_threshold, dim3((q + 255) / 256), dim3(256), 0, s, ws, q);
+}
+
+// ---------------------------------------------------------------------------
+// Single-query scan: HBM-bound stream over the query's ranges.  A wave covers
+// a 512-record tile per iteration: every lane loads two consecutive records of
+// each word array with one 16-byte load (4 x 3 loads in flight per lane).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_scan_single(Lib lib, Workspace ws, uint32_t qidx,
+                                                     uint64_t tiles) {
+  const QueryInfo *qi = ws.qinfo + qidx;
+  const uint64_t q0 = qi->w[0], q1 = qi->w[1], q2 = qi->w[2];
+  const int32_t T = (int32_t)ws.T[qidx];
+  const RangeSet *rs = ws.rsets + qi->rset;
+  uint32_t *cnt = ws.count + qidx;
+  uint64_t *cand = ws.cand + qi->cand_off;
+  const uint32_t cap = qi->cap;
+  const uint32_t lane = lane_id();
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  uint32_t r = 0;
+  for (uint64_t t = wave; t < tiles; t += nwaves) {
+    while (t >= rs->t1off[r + 1]) ++r;
+    const uint64_t rb = rs->begin[r], re = rs->end[r];
+    const uint64_t base = (rb & ~(uint64_t)(kScanTile - 1)) + (t - rs->t1off[r]) * kScanTile;
+    ulonglong2 a[4], b[4], c[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint64_t i = base + 128 * u + 2 * lane;
+      a[u] = *reinterpret_cast<const ulonglong2 *>(lib.w0 + i);
+      b[u] = *reinterpret_cast<const ulonglong2 *>(lib.w1 + i);
+      c[u] = *reinterpret_cast<const ulonglong2 *>(lib.w2 + i);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint64_t i = base + 128 * u + 2 * lane;
+      const int32_t d0 = (int32_t)dist3(a[u].x, b[u].x, c[u].x, q0, q1, q2);
+      const int32_t d1 = (int32_t)dist3(a[u].y, b[u].y, c[u].y, q0, q1, q2);
+      const bool h0 = d0 <= T && i >= rb && i < re;
+      const bool h1 = d1 <= T && i + 1 >= rb && i + 1 < re;
+      wave_append(h0, ((uint64_t)d0 << 32) | i, cnt, cand, cap);
+      wave_append(h1, ((uint64_t)d1 << 32) | (i + 1), cnt, cand, cap);
+    }
+  }
+}
+
+void launch_scan_single(const Lib &lib, const Workspace &ws, uint32_t qidx, uint64_t tiles,
+                        int cus, hipStream_t s) {
+  if (tiles == 0) return;
+  uint64_t blocks = (tiles + 3) / 4;  // 4 waves per block
+  const uint64_t maxb = (uint64_t)cus * 8;
+  if (blocks > maxb) blocks = maxb;
+  hipLaunchKernelGGL(k_scan_single, dim3((uint32_t)blocks), dim3(256), 0, s, lib, ws, qidx,
+                     tiles);
+}
+
+// ---------------------------------------------------------------------------
+// Batched popcount scan: a block takes a 2048-record tile of a query block's
+// range, holds 4 records per lane in registers and walks the block's queries
+// (staged in LDS).  Per pair: 3 XOR + 6 popcount-accumulate, seeded with
+// -(T+1) so that a candidate is exactly a negative sum.
+// ---------------------------------------------------------------------------
+constexpr int kPopRL = 4;
+
+__global__ __launch_bounds__(256) void k_scan_popcount(Lib lib, Workspace ws, uint32_t nqb,
+                                                       uint64_t items) {
+  __shared__ uint64_t qw[kPopQBlock][4];  // w0, w1, w2, -(T+1)
+  __shared__ uint32_t qid[kPopQBlock];
+  uint32_t cur_qb = 0xFFFFFFFFu;
+  QBlock qb{};
+  const uint32_t tid = threadIdx.x;
+  for (uint64_t item = blockIdx.x; item < items; item += gridDim.x) {
+    uint32_t b = 0;
+    while (b + 1 < nqb && item >= ws.qb_item_off[b + 1]) ++b;
+    if (b != cur_qb) {
+      __syncthreads();
+      cur_qb = b;
+      qb = ws.qblocks[b];
+      for (uint32_t j = tid; j < qb.count; j += blockDim.x) {
+        const uint32_t q = ws.perm[qb.first + j];
+        qid[j] = q;
+        qw[j][0] = ws.qinfo[q].w[0];
+        qw[j][1] = ws.qinfo[q].w[1];
+        qw[j][2] = ws.qinfo[q].w[2];
+        qw[j][3] = (uint64_t)(uint32_t)(-((int32_t)ws.T[q] + 1));
+      }
+      __syncthreads();
+    }
+    const RangeSet *rs = ws.rsets + qb.rset;
+    const uint64_t tile = item - ws.qb_item_off[b];
+    uint32_t r = 0;
+    while (tile >= rs->tboff[r + 1]) ++r;
+    const uint64_t g0 = rs->begin[r] + (tile - rs->tboff[r]) * kBatchTile;
+    const uint64_t g1 = min(g0 + (uint64_t)kBatchTile, rs->end[r]);
+    for (uint64_t sub = g0; sub < g1; sub += 256 * kPopRL) {
+      uint64_t x0[kPopRL], x1[kPopRL], x2[kPopRL];
+      bool ok[kPopRL];
+#pragma unroll
+      for (int u = 0; u < kPopRL; ++u) {
+        const uint64_t g = sub + 256 * u + tid;
+        ok[u] = g < g1;
+        const uint64_t gs = ok[u] ? g : g0;
+        x0[u] = lib.w0[gs];
+        x1[u] = lib.w1[gs];
+        x2[u] = lib.w2[gs];
+      }
+      for (uint32_t j = 0; j < qb.count; ++j) {
+        const uint64_t q0 = qw[j][0], q1 = qw[j][1], q2 = qw[j][2];
+        const int32_t seed = (int32_t)(uint32_t)qw[j][3];
+        int32_t v[kPopRL];
+        int32_t any = 0;
+#pragma unroll
+        for (int u = 0; u < kPopRL; ++u) {
+          v[u] = seed + (int32_t)dist3(x0[u], x1[u], x2[u], q0, q1, q2);
+          any |= v[u];
+        }
+        if (__ballot(any < 0) == 0) continue;
+        const uint32_t q = qid[j];
+        const QueryInfo *qi = ws.qinfo + q;
+        const int32_t T1 = -seed;  // T + 1
+#pragma unroll
+        for (int u = 0; u < kPopRL; ++u) {
+          const uint64_t g = sub + 256 * u + tid;
+          const bool hit = ok[u] && v[u] < 0;
+          wave_append(hit, ((uint64_t)(uint32_t)(v[u] + T1) << 32) | g, ws.count + q,
+                      ws.cand + qi->cand_off, qi->cap);
+        }
+      }
+    }
+  }
+}
+
+void launch_scan_popcount(const Lib &lib, const Workspace &ws, uint32_t nqb, uint64_t items,
+                          int cus, hipStream_t s) {
+  if (items == 0) return;
+  uint64_t blocks = items;
+  const uint64_t maxb = (uint64_t)cus * 8;
+  if (blocks > maxb) blocks = maxb;
+  hipLaunchKernelGGL(k_scan_popcount, dim3((uint32_t)blocks), dim3(256), 0, s, lib, ws, nqb,
+                     items);
+}
+
+// ---------------------------------------------------------------------------
+// Select: one block per query.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_select(Workspace ws) {
+  __shared__ uint32_t hist[kBins];
+  __shared__ uint64_t keys[kSortCap];
+  __shared__ uint32_t s_dk, s_fail, s_ncoll;
+  const uint32_t q = blockIdx.x;
+  const QueryInfo *qi = ws.qinfo + q;
+  const uint32_t keff = qi->keff;
+  const uint32_t tid = threadIdx.x;
+  if (keff == 0) return;
+  const uint32_t n = ws.count[q];
+  if (n > qi->cap) {
+    if (tid == 0) ws.flags[q] |= 1u;
+    return;
+  }
+  const uint64_t *cand = ws.cand + qi->cand_off;
+  for (uint32_t i = tid; i < kBins; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  for (uint32_t i = tid; i < n; i += blockDim.x) atomicAdd(&hist[(uint32_t)(cand[i] >> 32)], 1u);
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t cum = 0, dk = 0xFFFFFFFFu;
+    for (uint32_t t = 0; t <= (uint32_t)kKeys; ++t) {
+      cum += hist[t];
+      if (cum >= keff) {
+        dk = t;
+        break;
+      }
+    }
+    s_fail = 0;
+    if (dk == 0xFFFFFFFFu) s_fail = 4u;
+    else if (cum > kSortCap) s_fail = 2u;
+    s_dk = dk;
+    s_ncoll = 0;
+  }
+  __syncthreads();
+  if (s_fail) {
+    if (tid == 0) ws.flags[q] |= s_fail;
+    return;
+  }
+  const uint32_t dk = s_dk;
+  for (uint32_t i = tid; i < n; i += blockDim.x) {
+    const uint64_t key = cand[i];
+    if ((uint32_t)(key >> 32) <= dk) keys[atomicAdd(&s_ncoll, 1u)] = key;
+  }
+  __syncthreads();
+  const uint32_t m = s_ncoll;
+  uint32_t P = 1;
+  while (P < m) P <<= 1;
+  for (uint32_t i = m + tid; i < P; i += blockDim.x) keys[i] = ~0ull;
+  __syncthreads();
+  for (uint32_t k = 2; k <= P; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = tid; i < P; i += blockDim.x) {
+        const uint32_t ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t a = keys[i], b = keys[ixj];
+          const bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            keys[i] = b;
+            keys[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  fps_hit *out = ws.out + qi->out_off;
+  for (uint32_t i = tid; i < keff; i += blockDim.x) {
+    const uint64_t key = keys[i];
+    out[i].index = (uint32_t)key;
+    out[i].distance = (uint32_t)(key >> 32);
+  }
+}
+
+void launch_select(const Workspace &ws, uint32_t q, hipStream_t s) {
+  if (q == 0) return;
+  hipLaunchKernelGGL(k_select, dim3(q), dim3(1024), 0, s, ws);
+}
+
+// ---------------------------------------------------------------------------
+// Exact ordered fallback for one query.  Every wave owns a contiguous chunk of
+// the query's virtual range.
+//   pass 1: per-wave distance histograms;
+//   scan:   per-bin exclusive prefix over waves, and bin totals;
+//   pass 2: every record with d <= D_k goes to position
+//           cum(d-1) + (records with the same d in earlier waves)
+//                    + (records with the same d earlier in this wave),
+//           i.e. its rank in (distance, index) order; positions < keff are
+//           written.  No sort is needed.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_fb_hist(Lib lib, Workspace ws, uint32_t qidx,
+                                                 uint64_t neff, uint64_t chunk) {
+  __shared__ uint32_t h[4][kBins];
+  const QueryInfo *qi = ws.qinfo + qidx;
+  const RangeSet *rs = ws.rsets + qi->rset;
+  const uint64_t q0 = qi->w[0], q1 = qi->w[1], q2 = qi->w[2];
+  const uint32_t wl = threadIdx.x >> 6, lane = lane_id();
+  const uint64_t w = (uint64_t)blockIdx.x * 4 + wl;
+  for (uint32_t i = threadIdx.x; i < 4 * kBins; i += blockDim.x) (&h[0][0])[i] = 0;
+  __syncthreads();
+  const uint64_t v0 = w * chunk, v1 = min(v0 + chunk, neff);
+  for (uint64_t v = v0 + lane; v < v1; v += 64) {
+    const uint64_t g = v2g(rs, v);
+    atomicAdd(&h[wl][dist3(lib.w0[g], lib.w1[g], lib.w2[g], q0, q1, q2)], 1u);
+  }
+  __syncthreads();
+  for (uint32_t b = lane; b < (uint32_t)kBins; b += 64) ws.fb_wave_hist[w * kBins + b] = h[wl][b];
+}
+
+__global__ __launch_bounds__(256) void k_fb_scan(Workspace ws) {
+  __shared__ uint32_t part[256];
+  const uint32_t bin = blockIdx.x, tid = threadIdx.x;
+  uint32_t carry = 0;
+  for (uint32_t w0 = 0; w0 < (uint32_t)kFbWaves; w0 += 256) {
+    const uint32_t x = ws.fb_wave_hist[(uint64_t)(w0 + tid) * kBins + bin];
+    part[tid] = x;
+    __syncthreads();
+    for (uint32_t off = 1; off < 256; off <<= 1) {
+      const uint32_t y = tid >= off ? part[tid - off] : 0;
+      __syncthreads();
+      part[tid] += y;
+      __syncthreads();
+    }
+    ws.fb_wave_off[(uint64_t)(w0 + tid) * kBins + bin] = carry + part[tid] - x;
+    carry += part[255];
+    __syncthreads();
+  }
+  if (tid == 0) ws.fb_bin_total[bin] = carry;
+}
+
+__global__ __launch_bounds__(256) void k_fb_emit(Lib lib, Workspace ws, uint32_t qidx,
+                                                 uint64_t neff, uint64_t chunk) {
+  __shared__ uint32_t cumex[kBins];
+  __shared__ uint32_t run[4][kBins];
+  __shared__ uint32_t s_dk;
+  const QueryInfo *qi = ws.qinfo + qidx;
+  const RangeSet *rs = ws.rsets + qi->rset;
+  const uint64_t q0 = qi->w[0], q1 = qi->w[1], q2 = qi->w[2];
+  const uint32_t keff = qi->keff;
+  fps_hit *out = ws.out + qi->out_off;
+  const uint32_t wl = threadIdx.x >> 6, lane = lane_id();
+  const uint64_t w = (uint64_t)blockIdx.x * 4 + wl;
+  for (uint32_t i = threadIdx.x; i < 4 * kBins; i += blockDim.x) (&run[0][0])[i] = 0;
+  if (threadIdx.x == 0) {
+    uint32_t cum = 0, dk = (uint32_t)kKeys;
+    bool found = false;
+    for (uint32_t t = 0; t < (uint32_t)kBins; ++t) {
+      cumex[t] = cum;
+      cum += (t <= (uint32_t)kKeys) ? ws.fb_bin_total[t] : 0;
+      if (!found && cum >= keff) {
+        dk = t;
+        found = true;
+      }
+    }
+    s_dk = dk;
+  }
+  __syncthreads();
+  const uint32_t dk = s_dk;
+  const uint64_t v0 = w * chunk, v1 = min(v0 + chunk, neff);
+  const uint32_t *woff = ws.fb_wave_off + w * kBins;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  for (uint64_t step = 0; step < chunk; step += 64) {
+    const uint64_t v = v0 + step + lane;
+    uint32_t d = 0;
+    uint64_t g = 0;
+    bool act = false;
+    if (v < v1) {
+      g = v2g(rs, v);
+      d = dist3(lib.w0[g], lib.w1[g], lib.w2[g], q0, q1, q2);
+      act = d <= dk;
+    }
+    uint64_t eq = __ballot(act);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool set = (d >> bit) & 1u;
+      const uint64_t bb = __ballot(act && set);
+      eq &= set ? bb : ~bb;
+    }
+    uint32_t pos = 0xFFFFFFFFu;
+    if (act) {
+      pos = cumex[d] + woff[d] + run[wl][d] + (uint32_t)__popcll(eq & lt);
+      if (pos < keff) {
+        out[pos].index = (uint32_t)g;
+        out[pos].distance = d;
+      }
+    }
+    __syncthreads();
+    if (act && (eq & ~(lt | (1ull << lane))) == 0) run[wl][d] += (uint32_t)__popcll(eq);
+    __syncthreads();
+  }
+}
+
+void launch_fallback(const Lib &lib, const Workspace &ws, uint32_t qidx, uint64_t neff,
+                     hipStream_t s) {
+  uint64_t chunk = (neff + kFbWaves - 1) / kFbWaves;
+  chunk = (chunk + 63) & ~(uint64_t)63;
+  if (chunk == 0) chunk = 64;
+  hipLaunchKernelGGL(k_fb_hist, dim3(kFbBlocks), dim3(256), 0, s, lib, ws, qidx, neff, chunk);
+  hipLaunchKernelGGL(k_fb_scan, dim3(kBins), dim3(256), 0, s, ws);
+  hipLaunchKernelGGL(k_fb_emit, dim3(kFbBlocks), dim3(256), 0, s, lib, ws, qidx, neff, chunk);
+}
+
+}  // namespace fps

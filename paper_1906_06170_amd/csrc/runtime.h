@@ -1,0 +1,59 @@
+// Host-side state of the C ABI shared by the runtime and the server.
+#pragma once
+#include <map>
+#include <vector>
+
+#include "fps_internal.h"
+
+constexpr uint64_t kDefaultSample = 1ull << 20;
+
+// Host state of one search in flight: pinned staging, timing events, counters.
+// The handle owns one; every server slot owns its own, so slots can run
+// concurrently on their own streams.
+struct SearchCtx {
+  void *h_params = nullptr;
+  size_t h_params_bytes = 0;
+  void *h_out = nullptr;
+  size_t h_out_bytes = 0;
+  hipEvent_t ev[4] = {};
+  fps_search_stats last{};
+  fps_status init();
+  ~SearchCtx();
+};
+
+struct fps_library {
+  uint64_t n = 0, np = 0;
+  uint32_t nstrides = 0;
+  uint64_t strides[FPS_MAX_STRIDES + 1] = {};
+  uint64_t *dev = nullptr;  // caller-owned rows: w0 = dev, w1 = dev + np, w2 = dev + 2 np
+  int device = 0;
+  int cus = 256;
+  fps_path path = FPS_PATH_AUTO;
+  double cand_scale = 1.0;
+  uint64_t sample = kDefaultSample;
+  int force_fb = 0;
+  SearchCtx ctx;  // staging of direct calls on this handle
+};
+
+// A planned search: per-query parameters and the byte layout of the workspace.
+struct Plan {
+  uint32_t q = 0;
+  std::vector<fps::RangeSet> rsets;
+  std::vector<fps::QueryInfo> qinfo;
+  std::vector<uint32_t> perm;
+  uint64_t total_cand = 0, total_out = 0, max_sample = 0;
+  size_t off_rsets = 0, off_qinfo = 0, off_perm = 0, off_qblocks = 0, off_qbitem = 0,
+         off_bblocks = 0, params_bytes = 0;
+  size_t off_T = 0, off_count = 0, off_flags = 0, off_hist = 0, off_cand = 0, off_out = 0,
+         off_fbh = 0, off_fbo = 0, off_fbt = 0, total_bytes = 0;
+};
+
+fps_status fps_fail(fps_status s, const char *fmt, ...);
+void fps_clear_error();
+fps_status fps_make_rangeset(const fps_library *lib, uint32_t mask, fps::RangeSet *rs);
+fps_status fps_plan(const fps_library *lib, uint32_t q, const uint32_t *k, const uint32_t *mask,
+                    Plan *P);
+fps_status fps_search_impl(fps_library *lib, SearchCtx *ctx, const uint64_t *queries, uint32_t q,
+                           const uint32_t *k, const uint32_t *mask, void *workspace,
+                           size_t ws_bytes, fps_hit *out, uint64_t out_capacity,
+                           uint64_t *out_offset, hipStream_t s, fps_path forced);

@@ -1,0 +1,552 @@
+// Host runtime of the C ABI (include/fps.h): library upload, workspace
+// planning, the launch sequence of a search, the exact fallback, statistics and
+// the batch-path autotuner.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "fps_internal.h"
+#include "runtime.h"
+
+using namespace fps;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string t_err;
+
+fps_status fps_fail(fps_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  t_err = buf;
+  return s;
+}
+
+void fps_clear_error() { t_err.clear(); }
+
+extern "C" const char *fps_last_error(void) { return t_err.c_str(); }
+
+#define HIP_TRY(x)                                                                         \
+  do {                                                                                     \
+    hipError_t e_ = (x);                                                                   \
+    if (e_ != hipSuccess) return fps_fail(FPS_E_DEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+
+static inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+static bool bad_fingerprint(const uint64_t *w) {
+  return (w[0] & 1ull) != 0 || (w[2] >> 39) != 0;
+}
+
+// ---------------------------------------------------------------------------
+// pinned staging
+// ---------------------------------------------------------------------------
+static fps_status ensure_pinned(void **p, size_t *have, size_t need) {
+  if (*have >= need && *p) return FPS_OK;
+  if (*p) {
+    (void)hipHostFree(*p);
+    *p = nullptr;
+    *have = 0;
+  }
+  size_t n = align_up(std::max<size_t>(need, 1 << 16), 1 << 16);
+  HIP_TRY(hipHostMalloc(p, n, hipHostMallocDefault));
+  *have = n;
+  return FPS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// library
+// ---------------------------------------------------------------------------
+extern "C" size_t fps_library_device_bytes(uint64_t n) {
+  const uint64_t np = (n + kRowAlign - 1) / kRowAlign * kRowAlign;
+  return (size_t)(np * 3 * sizeof(uint64_t));
+}
+
+SearchCtx::~SearchCtx() {
+  if (h_params) (void)hipHostFree(h_params);
+  if (h_out) (void)hipHostFree(h_out);
+  for (auto &e : ev)
+    if (e) (void)hipEventDestroy(e);
+}
+
+fps_status SearchCtx::init() {
+  for (auto &e : ev)
+    if (!e) HIP_TRY(hipEventCreate(&e));
+  return FPS_OK;
+}
+
+extern "C" fps_status fps_library_load(const uint64_t *host_words, uint64_t n,
+                                       const uint64_t *stride_begin, uint32_t nstrides,
+                                       void *device_buf, size_t device_bytes, void *stream,
+                                       fps_library **out) {
+  fps_clear_error();
+  if (!host_words || !device_buf || !out) return fps_fail(FPS_E_ARG, "NULL argument");
+  if (n == 0 || n >= (1ull << 32)) return fps_fail(FPS_E_ARG, "n = %llu out of range", (unsigned long long)n);
+  if (device_bytes < fps_library_device_bytes(n))
+    return fps_fail(FPS_E_ARG, "device buffer of %zu bytes < %zu needed", device_bytes,
+                    fps_library_device_bytes(n));
+  if (((uintptr_t)device_buf & 255) != 0)
+    return fps_fail(FPS_E_ARG, "device buffer must be 256-byte aligned");
+  std::vector<uint64_t> st;
+  if (!stride_begin) {
+    st = {0, n};
+  } else {
+    if (nstrides < 1 || nstrides > FPS_MAX_STRIDES)
+      return fps_fail(FPS_E_ARG, "nstrides = %u out of range", nstrides);
+    st.assign(stride_begin, stride_begin + nstrides + 1);
+    if (st[0] != 0 || st[nstrides] != n)
+      return fps_fail(FPS_E_ARG, "stride offsets must start at 0 and end at n");
+    for (uint32_t s = 0; s < nstrides; ++s)
+      if (st[s + 1] < st[s]) return fps_fail(FPS_E_ARG, "stride offsets must not decrease");
+  }
+  for (uint64_t i = 0; i < n; ++i)
+    if (bad_fingerprint(host_words + 3 * i))
+      return fps_fail(FPS_E_FINGERPRINT, "record %llu has bit 0 or a bit above key 166 set",
+                      (unsigned long long)i);
+  auto *L = new (std::nothrow) fps_library();
+  if (!L) return fps_fail(FPS_E_NOMEM, "host allocation failed");
+  L->n = n;
+  L->np = (n + kRowAlign - 1) / kRowAlign * kRowAlign;
+  L->nstrides = (uint32_t)st.size() - 1;
+  std::copy(st.begin(), st.end(), L->strides);
+  L->dev = (uint64_t *)device_buf;
+  hipStream_t s = (hipStream_t)stream;
+  fps_status rc = FPS_OK;
+  do {
+    if (hipGetDevice(&L->device) != hipSuccess ||
+        hipDeviceGetAttribute(&L->cus, hipDeviceAttributeMultiprocessorCount, L->device) !=
+            hipSuccess) {
+      rc = fps_fail(FPS_E_DEVICE, "cannot query the current device");
+      break;
+    }
+    if ((rc = L->ctx.init())) break;
+    // transpose record-major host words to word-major device rows, in chunks
+    const uint64_t CH = 1u << 20;
+    void *pin = nullptr;
+    size_t pin_bytes = 0;
+    if ((rc = ensure_pinned(&pin, &pin_bytes, 3 * CH * sizeof(uint64_t)))) break;
+    uint64_t *stage = (uint64_t *)pin;
+    for (uint64_t c0 = 0; c0 < n && !rc; c0 += CH) {
+      const uint64_t c1 = std::min(n, c0 + CH), m = c1 - c0;
+      if (hipStreamSynchronize(s) != hipSuccess) {
+        rc = fps_fail(FPS_E_DEVICE, "stream synchronize failed");
+        break;
+      }
+      for (uint64_t i = 0; i < m; ++i) {
+        stage[i] = host_words[3 * (c0 + i)];
+        stage[CH + i] = host_words[3 * (c0 + i) + 1];
+        stage[2 * CH + i] = host_words[3 * (c0 + i) + 2];
+      }
+      for (int w = 0; w < 3; ++w)
+        if (hipMemcpyAsync(L->dev + w * L->np + c0, stage + w * CH, m * sizeof(uint64_t),
+                           hipMemcpyHostToDevice, s) != hipSuccess)
+          rc = fps_fail(FPS_E_DEVICE, "upload failed");
+    }
+    if (!rc && L->np > n)
+      for (int w = 0; w < 3; ++w)
+        if (hipMemsetAsync(L->dev + w * L->np + n, 0, (L->np - n) * sizeof(uint64_t), s) !=
+            hipSuccess)
+          rc = fps_fail(FPS_E_DEVICE, "hipMemsetAsync failed");
+    if (!rc && hipStreamSynchronize(s) != hipSuccess)
+      rc = fps_fail(FPS_E_DEVICE, "stream synchronize failed");
+    (void)hipHostFree(pin);
+  } while (0);
+  if (rc) {
+    delete L;
+    return rc;
+  }
+  *out = L;
+  return FPS_OK;
+}
+
+extern "C" fps_status fps_library_info(const fps_library *lib, uint64_t *n, uint32_t *nstrides,
+                                       uint64_t *stride_begin) {
+  fps_clear_error();
+  if (!lib) return fps_fail(FPS_E_ARG, "NULL library");
+  if (n) *n = lib->n;
+  if (nstrides) *nstrides = lib->nstrides;
+  if (stride_begin) std::copy(lib->strides, lib->strides + lib->nstrides + 1, stride_begin);
+  return FPS_OK;
+}
+
+extern "C" fps_status fps_library_free(fps_library *lib) {
+  fps_clear_error();
+  delete lib;
+  return FPS_OK;
+}
+
+extern "C" fps_status fps_set_path(fps_library *lib, fps_path path) {
+  fps_clear_error();
+  if (!lib) return fps_fail(FPS_E_ARG, "NULL library");
+  if ((int)path < 0 || (int)path > (int)FPS_PATH_MFMA_F4)
+    return fps_fail(FPS_E_ARG, "unknown path %d", (int)path);
+  lib->path = path;
+  return FPS_OK;
+}
+
+extern "C" fps_status fps_set_tuning(fps_library *lib, double candidate_scale,
+                                     uint64_t sample_records, int force_fallback) {
+  fps_clear_error();
+  if (!lib) return fps_fail(FPS_E_ARG, "NULL library");
+  if (!(candidate_scale > 0.0) || !std::isfinite(candidate_scale))
+    return fps_fail(FPS_E_ARG, "candidate_scale must be positive");
+  lib->cand_scale = candidate_scale;
+  lib->sample = sample_records ? sample_records : kDefaultSample;
+  lib->force_fb = force_fallback;
+  return FPS_OK;
+}
+
+extern "C" fps_status fps_last_search_stats(const fps_library *lib, fps_search_stats *stats) {
+  fps_clear_error();
+  if (!lib || !stats) return fps_fail(FPS_E_ARG, "NULL argument");
+  *stats = lib->ctx.last;
+  return FPS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// planning
+// ---------------------------------------------------------------------------
+fps_status fps_make_rangeset(const fps_library *lib, uint32_t mask, RangeSet *rs) {
+  const uint32_t ns = lib->nstrides;
+  uint32_t m = mask;
+  if (mask == FPS_MASK_ALL) m = ns >= 32 ? 0xFFFFFFFFu : ((1u << ns) - 1u);
+  if (m == 0) return fps_fail(FPS_E_ARG, "stride mask is zero");
+  if (ns < 32 && (m >> ns) != 0)
+    return fps_fail(FPS_E_ARG, "stride mask 0x%x names a stride the library lacks", mask);
+  std::memset(rs, 0, sizeof *rs);
+  rs->mask = m;
+  for (uint32_t s = 0; s < ns; ++s) {
+    if (!((m >> s) & 1u)) continue;
+    const uint64_t b = lib->strides[s], e = lib->strides[s + 1];
+    if (b == e) continue;
+    if (rs->nranges > 0 && rs->end[rs->nranges - 1] == b) {
+      rs->end[rs->nranges - 1] = e;  // adjacent strides form one range
+    } else {
+      rs->begin[rs->nranges] = b;
+      rs->end[rs->nranges] = e;
+      rs->nranges++;
+    }
+  }
+  uint64_t v = 0, t1 = 0, tb = 0;
+  for (uint32_t r = 0; r < rs->nranges; ++r) {
+    rs->voff[r] = v;
+    rs->t1off[r] = t1;
+    rs->tboff[r] = tb;
+    const uint64_t len = rs->end[r] - rs->begin[r];
+    v += len;
+    t1 += (rs->end[r] + kScanTile - 1) / kScanTile - rs->begin[r] / kScanTile;
+    tb += (len + kBatchTile - 1) / kBatchTile;
+  }
+  for (uint32_t r = rs->nranges; r <= FPS_MAX_STRIDES; ++r) {
+    rs->voff[r] = v;
+    rs->t1off[r] = t1;
+    rs->tboff[r] = tb;
+  }
+  rs->neff = v;
+  return FPS_OK;
+}
+
+static uint32_t capacity(const fps_library *lib, uint64_t keff, uint64_t neff, uint64_t sample) {
+  if (keff == 0 || neff == 0) return 0;
+  const double expected = sample ? (double)keff * (double)neff / (double)sample : (double)neff;
+  double cap = lib->cand_scale * (8.0 * expected + 4096.0);
+  cap = std::min(cap, (double)neff);
+  cap = std::max(cap, 1.0);
+  return (uint32_t)std::ceil(cap);
+}
+
+fps_status fps_plan(const fps_library *lib, uint32_t q, const uint32_t *k, const uint32_t *mask,
+                    Plan *P) {
+  if (q == 0) return fps_fail(FPS_E_ARG, "q must be >= 1");
+  if (!k) return fps_fail(FPS_E_ARG, "NULL k");
+  P->q = q;
+  P->rsets.clear();
+  P->qinfo.assign(q, QueryInfo{});
+  std::map<uint32_t, uint32_t> seen;
+  P->total_cand = 0;
+  P->total_out = 0;
+  P->max_sample = 0;
+  for (uint32_t i = 0; i < q; ++i) {
+    const uint32_t m = mask ? mask[i] : FPS_MASK_ALL;
+    auto it = seen.find(m);
+    uint32_t id;
+    if (it == seen.end()) {
+      RangeSet rs;
+      fps_status rc = fps_make_rangeset(lib, m, &rs);
+      if (rc) return rc;
+      id = (uint32_t)P->rsets.size();
+      P->rsets.push_back(rs);
+      seen[m] = id;
+    } else {
+      id = it->second;
+    }
+    const RangeSet &rs = P->rsets[id];
+    QueryInfo &qi = P->qinfo[i];
+    qi.rset = id;
+    qi.keff = (uint32_t)std::min<uint64_t>(k[i], rs.neff);
+    qi.sample = std::min<uint64_t>(lib->sample, rs.neff);
+    qi.cap = capacity(lib, qi.keff, rs.neff, qi.sample);
+    qi.cand_off = P->total_cand;
+    qi.out_off = P->total_out;
+    P->total_cand += qi.cap;
+    P->total_out += qi.keff;
+    if (qi.keff) P->max_sample = std::max(P->max_sample, qi.sample);
+  }
+  // sizes: parameter region (uploaded), then device-computed state
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  const size_t maxqb = (size_t)q + P->rsets.size() + 1;
+  P->off_rsets = take(P->rsets.size() * sizeof(RangeSet));
+  P->off_qinfo = take((size_t)q * sizeof(QueryInfo));
+  P->off_perm = take((size_t)q * sizeof(uint32_t));
+  P->off_qblocks = take(maxqb * sizeof(QBlock));
+  P->off_qbitem = take((maxqb + 1) * sizeof(uint64_t));
+  P->off_bblocks = take(maxqb * sizeof(QBlock));
+  P->params_bytes = off;
+  P->off_T = take((size_t)q * 4);
+  P->off_count = take((size_t)q * 4);
+  P->off_flags = take((size_t)q * 4);
+  P->off_hist = take((size_t)q * kBins * 4);
+  P->off_cand = take(P->total_cand * sizeof(uint64_t));
+  P->off_out = take(P->total_out * sizeof(fps_hit));
+  P->off_fbh = take((size_t)kFbWaves * kBins * 4);
+  P->off_fbo = take((size_t)kFbWaves * kBins * 4);
+  P->off_fbt = take((size_t)kBins * 4);
+  P->total_bytes = off;
+  return FPS_OK;
+}
+
+extern "C" fps_status fps_workspace_bytes(const fps_library *lib, uint32_t q, const uint32_t *k,
+                                          const uint32_t *mask, size_t *bytes) {
+  fps_clear_error();
+  if (!lib || !bytes) return fps_fail(FPS_E_ARG, "NULL argument");
+  Plan P;
+  fps_status rc = fps_plan(lib, q, k, mask, &P);
+  if (rc) return rc;
+  *bytes = P.total_bytes;
+  return FPS_OK;
+}
+
+// Groups queries by RangeSet into blocks of at most `qbs` queries; fills perm,
+// the blocks and the per-block work-item prefix (tiles of the block's range).
+void fps_make_blocks(Plan *P, uint32_t qbs, std::vector<QBlock> *blocks,
+                     std::vector<uint64_t> *item_off, bool items_single_tiles) {
+  P->perm.clear();
+  blocks->clear();
+  item_off->clear();
+  uint64_t items = 0;
+  for (uint32_t r = 0; r < P->rsets.size(); ++r) {
+    const uint32_t first = (uint32_t)P->perm.size();
+    for (uint32_t i = 0; i < P->q; ++i)
+      if (P->qinfo[i].rset == r && P->qinfo[i].keff > 0) P->perm.push_back(i);
+    const uint32_t cnt = (uint32_t)P->perm.size() - first;
+    const RangeSet &rs = P->rsets[r];
+    const uint64_t tiles = items_single_tiles ? rs.t1off[rs.nranges] : rs.tboff[rs.nranges];
+    for (uint32_t f = 0; f < cnt; f += qbs) {
+      QBlock b{};
+      b.first = first + f;
+      b.count = std::min(qbs, cnt - f);
+      b.rset = r;
+      blocks->push_back(b);
+      item_off->push_back(items);
+      items += tiles;
+    }
+  }
+  item_off->push_back(items);
+  // queries with keff = 0 go last (never scanned)
+  for (uint32_t i = 0; i < P->q; ++i)
+    if (P->qinfo[i].keff == 0) P->perm.push_back(i);
+}
+
+// ---------------------------------------------------------------------------
+// search
+// ---------------------------------------------------------------------------
+static Workspace ws_view(const Plan &P, uint8_t *base) {
+  Workspace w{};
+  w.rsets = (RangeSet *)(base + P.off_rsets);
+  w.qinfo = (QueryInfo *)(base + P.off_qinfo);
+  w.perm = (uint32_t *)(base + P.off_perm);
+  w.qblocks = (QBlock *)(base + P.off_qblocks);
+  w.qb_item_off = (uint64_t *)(base + P.off_qbitem);
+  w.bblocks = (QBlock *)(base + P.off_bblocks);
+  w.T = (uint32_t *)(base + P.off_T);
+  w.count = (uint32_t *)(base + P.off_count);
+  w.flags = (uint32_t *)(base + P.off_flags);
+  w.hist = (uint32_t *)(base + P.off_hist);
+  w.cand = (uint64_t *)(base + P.off_cand);
+  w.out = (fps_hit *)(base + P.off_out);
+  w.fb_wave_hist = (uint32_t *)(base + P.off_fbh);
+  w.fb_wave_off = (uint32_t *)(base + P.off_fbo);
+  w.fb_bin_total = (uint32_t *)(base + P.off_fbt);
+  return w;
+}
+
+static fps_path resolve_path(fps_library *lib, const Plan &P, fps_path requested, bool single);
+
+// Launches the whole search of a planned batch on stream s (no host sync).
+static fps_status launch_search(fps_library *lib, SearchCtx *ctx, Plan &P, fps_path path,
+                                uint8_t *wsbase, hipStream_t s) {
+  const Workspace ws = ws_view(P, wsbase);
+  Lib L{lib->dev, lib->dev + lib->np, lib->dev + 2 * lib->np, lib->n, lib->np};
+  // blocks for the bound kernel and for the batched scan
+  std::vector<QBlock> bblocks, qblocks;
+  std::vector<uint64_t> bitems, qitems;
+  fps_make_blocks(&P, kBoundQBlock, &bblocks, &bitems, false);
+  uint32_t qbs = path == FPS_PATH_MFMA_I8 ? (uint32_t)kMfmaQBlock : (uint32_t)kPopQBlock;
+  fps_make_blocks(&P, qbs, &qblocks, &qitems, false);
+  // parameter upload
+  fps_status rc = ensure_pinned(&ctx->h_params, &ctx->h_params_bytes, P.params_bytes);
+  if (rc) return rc;
+  uint8_t *h = (uint8_t *)ctx->h_params;
+  std::memcpy(h + P.off_rsets, P.rsets.data(), P.rsets.size() * sizeof(RangeSet));
+  std::memcpy(h + P.off_qinfo, P.qinfo.data(), P.q * sizeof(QueryInfo));
+  std::memcpy(h + P.off_perm, P.perm.data(), P.q * sizeof(uint32_t));
+  std::memcpy(h + P.off_qblocks, qblocks.data(), qblocks.size() * sizeof(QBlock));
+  std::memcpy(h + P.off_qbitem, qitems.data(), qitems.size() * sizeof(uint64_t));
+  std::memcpy(h + P.off_bblocks, bblocks.data(), bblocks.size() * sizeof(QBlock));
+  HIP_TRY(hipMemcpyAsync(wsbase, h, P.params_bytes, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipEventRecord(ctx->ev[0], s));
+  launch_prep(ws, P.q, s);
+  launch_bound(L, ws, (uint32_t)bblocks.size(), P.max_sample, s);
+  launch_threshold(ws, P.q, s);
+  HIP_TRY(hipEventRecord(ctx->ev[1], s));
+  if (path == FPS_PATH_SINGLE) {
+    for (uint32_t i = 0; i < P.q; ++i) {
+      const QueryInfo &qi = P.qinfo[i];
+      if (qi.keff == 0) continue;
+      const RangeSet &rs = P.rsets[qi.rset];
+      launch_scan_single(L, ws, i, rs.t1off[rs.nranges], lib->cus, s);
+    }
+  } else if (path == FPS_PATH_POPCOUNT) {
+    launch_scan_popcount(L, ws, (uint32_t)qblocks.size(), qitems.back(), lib->cus, s);
+  } else {
+    launch_scan_mfma_i8(L, ws, (uint32_t)qblocks.size(), qitems.back(), lib->cus, s);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventRecord(ctx->ev[2], s));
+  launch_select(ws, P.q, s);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventRecord(ctx->ev[3], s));
+  return FPS_OK;
+}
+
+fps_status fps_search_impl(fps_library *lib, SearchCtx *ctx, const uint64_t *queries, uint32_t q,
+                           const uint32_t *k, const uint32_t *mask, void *workspace,
+                           size_t ws_bytes, fps_hit *out, uint64_t out_capacity,
+                           uint64_t *out_offset, hipStream_t s, fps_path forced) {
+  if (!lib || !ctx || !queries || !k || !workspace || !out_offset)
+    return fps_fail(FPS_E_ARG, "NULL argument");
+  for (uint32_t i = 0; i < q; ++i)
+    if (bad_fingerprint(queries + 3 * (size_t)i))
+      return fps_fail(FPS_E_FINGERPRINT, "query %u has bit 0 or a bit above key 166 set", i);
+  Plan P;
+  fps_status rc = fps_plan(lib, q, k, mask, &P);
+  if (rc) return rc;
+  if (P.total_out > 0 && !out) return fps_fail(FPS_E_ARG, "NULL out");
+  if (out_capacity < P.total_out)
+    return fps_fail(FPS_E_ARG, "out holds %llu hits, %llu needed",
+                    (unsigned long long)out_capacity, (unsigned long long)P.total_out);
+  if (ws_bytes < P.total_bytes)
+    return fps_fail(FPS_E_NOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, P.total_bytes);
+  if (((uintptr_t)workspace & 255) != 0)
+    return fps_fail(FPS_E_ARG, "workspace must be 256-byte aligned");
+  for (uint32_t i = 0; i < q; ++i) {
+    std::memcpy(P.qinfo[i].w, queries + 3 * (size_t)i, 3 * sizeof(uint64_t));
+    P.qinfo[i].popc = (uint32_t)(__builtin_popcountll(P.qinfo[i].w[0]) +
+                                 __builtin_popcountll(P.qinfo[i].w[1]) +
+                                 __builtin_popcountll(P.qinfo[i].w[2]));
+  }
+  out_offset[0] = 0;
+  for (uint32_t i = 0; i < q; ++i) out_offset[i + 1] = out_offset[i] + P.qinfo[i].keff;
+  ctx->last = fps_search_stats{};
+  ctx->last.queries = q;
+  if (P.total_out == 0) return FPS_OK;
+  const fps_path path = resolve_path(lib, P, forced, false);
+  ctx->last.path = (uint32_t)path;
+  uint8_t *wsb = (uint8_t *)workspace;
+  rc = launch_search(lib, ctx, P, path, wsb, s);
+  if (rc) return rc;
+  // results and per-query status back to the host
+  const size_t out_bytes = P.total_out * sizeof(fps_hit);
+  const size_t stat_bytes = (size_t)q * 8;
+  rc = ensure_pinned(&ctx->h_out, &ctx->h_out_bytes, out_bytes + stat_bytes + 256);
+  if (rc) return rc;
+  uint8_t *ho = (uint8_t *)ctx->h_out;
+  uint32_t *h_count = (uint32_t *)(ho);
+  uint32_t *h_flags = (uint32_t *)(ho + (size_t)q * 4);
+  fps_hit *h_hits = (fps_hit *)(ho + align_up(stat_bytes, 256));
+  HIP_TRY(hipMemcpyAsync(h_count, wsb + P.off_count, (size_t)q * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(h_flags, wsb + P.off_flags, (size_t)q * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(h_hits, wsb + P.off_out, out_bytes, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  float ms = 0;
+  if (hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]) == hipSuccess) ctx->last.scan_ms = ms;
+  if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[3]) == hipSuccess) ctx->last.total_ms = ms;
+  const Workspace ws = ws_view(P, wsb);
+  Lib L{lib->dev, lib->dev + lib->np, lib->dev + 2 * lib->np, lib->n, lib->np};
+  for (uint32_t i = 0; i < q; ++i) {
+    ctx->last.candidates += h_count[i];
+    const QueryInfo &qi = P.qinfo[i];
+    if (qi.keff == 0) continue;
+    if (h_flags[i] == 0 && !lib->force_fb) continue;
+    ctx->last.fallbacks++;
+    launch_fallback(L, ws, i, P.rsets[qi.rset].neff, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(h_hits + qi.out_off, wsb + P.off_out + qi.out_off * sizeof(fps_hit),
+                           qi.keff * sizeof(fps_hit), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  std::memcpy(out, h_hits, out_bytes);
+  return FPS_OK;
+}
+
+extern "C" fps_status fps_search(fps_library *lib, const uint64_t query[3], uint32_t k,
+                                 uint32_t mask, void *workspace, size_t ws_bytes, fps_hit *out,
+                                 uint32_t *n_out, void *stream) {
+  fps_clear_error();
+  if (!n_out) return fps_fail(FPS_E_ARG, "NULL n_out");
+  uint64_t off[2] = {0, 0};
+  if (!lib) return fps_fail(FPS_E_ARG, "NULL library");
+  fps_status rc = fps_search_impl(lib, &lib->ctx, query, 1, &k, &mask, workspace, ws_bytes, out,
+                                  out ? (uint64_t)k : 0, off, (hipStream_t)stream,
+                                  FPS_PATH_SINGLE);
+  if (rc) return rc;
+  *n_out = (uint32_t)off[1];
+  return FPS_OK;
+}
+
+extern "C" fps_status fps_search_batch(fps_library *lib, const uint64_t *queries, uint32_t q,
+                                       const uint32_t *k, const uint32_t *mask, void *workspace,
+                                       size_t ws_bytes, fps_hit *out, uint64_t out_capacity,
+                                       uint64_t *out_offset, void *stream) {
+  fps_clear_error();
+  if (!lib) return fps_fail(FPS_E_ARG, "NULL library");
+  return fps_search_impl(lib, &lib->ctx, queries, q, k, mask, workspace, ws_bytes, out, out_capacity,
+                         out_offset, (hipStream_t)stream, FPS_PATH_AUTO);
+}
+
+// ---------------------------------------------------------------------------
+// path choice
+// ---------------------------------------------------------------------------
+static fps_path resolve_path(fps_library *lib, const Plan &P, fps_path requested, bool) {
+  if (requested != FPS_PATH_AUTO) return requested;
+  if (lib->path != FPS_PATH_AUTO) return lib->path == FPS_PATH_MFMA_F4 ? FPS_PATH_MFMA_I8 : lib->path;
+  uint32_t live = 0;
+  for (const auto &qi : P.qinfo) live += qi.keff > 0;
+  if (live >= 64) return FPS_PATH_MFMA_I8;
+  if (live >= 4) return FPS_PATH_POPCOUNT;
+  return FPS_PATH_SINGLE;
+}

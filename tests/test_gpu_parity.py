@@ -1,0 +1,239 @@
+"""GPU path vs the CPU oracle, element by element (ids, distances and order),
+on seeded synthetic libraries small enough for the oracle to finish in seconds.
+Integer results: the bar is bit-exact equality."""
+import numpy as np
+import pytest
+
+import fpsynth
+import oracle
+
+fps = pytest.importorskip("paper_1906_06170_amd")
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+PATHS = [fps.PATH_SINGLE, fps.PATH_POPCOUNT, fps.PATH_MFMA_I8]
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def small():
+    lib_np = fpsynth.make_library(100_000, 1)
+    strides = [0, 40_000, 75_000, 100_000]
+    lib = fps.Library(lib_np.words, strides=strides)
+    return lib_np, lib
+
+
+def check_batch(lib_np, lib, queries, k, masks=None, path=None, what=""):
+    if path is not None:
+        lib.set_path(path)
+    say("case:", what, "path", path, "q", len(queries))
+    hits, off = lib.search_batch(queries, k, masks)
+    ohits, ooff = oracle.search_batch(lib_np.words, queries, k, lib.strides, masks)
+    assert np.array_equal(off, ooff), what
+    if not np.array_equal(hits, ohits):
+        for i in range(len(queries)):
+            a = hits[int(off[i]):int(off[i + 1])]
+            b = ohits[int(ooff[i]):int(ooff[i + 1])]
+            assert np.array_equal(a, b), f"{what}: query {i} differs\n{a[:10]}\n{b[:10]}"
+    lib.set_path(fps.PATH_AUTO)
+    return lib.last_stats()
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_small_single_query_seeds(seed):
+    """100,000 records, a library record with 2 flips, top-30 (several seeds)."""
+    lib_np, q, k, _ = fpsynth.workload_small(seed)
+    lib = fps.Library(lib_np.words)
+    say("case: small seed", seed)
+    got = lib.search(q.words[0], 30)
+    want = oracle.search(lib_np.words, q.words[0], 30)
+    assert np.array_equal(got, want)
+    assert got["distance"][0] <= 2
+    st = lib.last_stats()
+    assert st["fallbacks"] == 0 and st["path"] == "single"
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 30, 1000, 8000, 99_999, 100_000, 100_007])
+def test_k_edges_single(small, k):
+    lib_np, lib = small
+    q = fpsynth.batch_queries(lib_np, 2, 11).words[1]
+    say("case: k edge", k)
+    got = lib.search(q, k)
+    want = oracle.search(lib_np.words, q, k)
+    assert len(got) == min(k, 100_000)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_batch_paths_uniform_k(small, path):
+    lib_np, lib = small
+    qs = fpsynth.batch_queries(lib_np, 300, 1003).words
+    st = check_batch(lib_np, lib, qs, 30, None, path, "uniform k=30")
+    assert st["path"] == fps.PATH_NAMES[path]
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_batch_paths_uneven_k_masks(small, path):
+    lib_np, lib = small
+    nq = 333
+    qs = fpsynth.batch_queries(lib_np, nq, 1004).words
+    k, masks = fpsynth.uneven_params(nq, 1004)
+    check_batch(lib_np, lib, qs, k, masks, path, "uneven k and masks")
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_all_masks_and_strides(small, path):
+    lib_np, lib = small
+    qs = fpsynth.batch_queries(lib_np, 7 * 5, 77).words
+    masks = np.repeat(np.arange(1, 8, dtype=np.uint32), 5)
+    k = np.tile(np.array([1, 10, 30, 100, 1000], dtype=np.uint32), 7)
+    check_batch(lib_np, lib, qs, k, masks, path, "every mask")
+
+
+@pytest.mark.parametrize("n", [1, 63, 511, 513, 2047, 2049, 4097, 33_333])
+@pytest.mark.parametrize("path", PATHS)
+def test_ragged_sizes(n, path):
+    lib_np = fpsynth.make_library(n, 100 + n)
+    lib = fps.Library(lib_np.words)
+    qs = fpsynth.batch_queries(lib_np, 70, n).words
+    for k in (1, 30, n):
+        check_batch(lib_np, lib, qs, k, None, path, f"n={n} k={k}")
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_odd_stride_boundaries(path):
+    n = 20_011
+    lib_np = fpsynth.make_library(n, 5)
+    strides = [0, 1, 2, 515, 1027, 1027, 9_999, 20_010, n]
+    lib = fps.Library(lib_np.words, strides=strides)
+    nq = 96
+    qs = fpsynth.batch_queries(lib_np, nq, 9).words
+    rng = np.random.default_rng(3)
+    masks = rng.integers(1, 256, size=nq).astype(np.uint32)
+    k = rng.choice(np.array([1, 3, 30, 500], dtype=np.uint32), size=nq)
+    check_batch(lib_np, lib, qs, k, masks, path, "odd strides")
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_forced_fallback(small, path):
+    lib_np, lib = small
+    qs = fpsynth.batch_queries(lib_np, 40, 5).words
+    k, masks = fpsynth.uneven_params(40, 6)
+    lib.set_tuning(force_fallback=True)
+    try:
+        st = check_batch(lib_np, lib, qs, k, masks, path, "forced fallback")
+        assert st["fallbacks"] == 40
+    finally:
+        lib.set_tuning()
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_overflow_fallback(small, path):
+    lib_np, lib = small
+    qs = fpsynth.batch_queries(lib_np, 70, 8).words
+    lib.set_tuning(candidate_scale=1e-6, sample_records=1024)
+    try:
+        st = check_batch(lib_np, lib, qs, 30, None, path, "overflow")
+        assert st["fallbacks"] > 0
+    finally:
+        lib.set_tuning()
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_identical_rows(path):
+    """100,000 identical rows: every record ties; k = 1 must return index 0."""
+    rec = fpsynth.make_library(1, 51).words[0]
+    words = np.tile(rec, (100_000, 1))
+    lib = fps.Library(words, strides=[0, 50_000, 100_000])
+    qs = np.stack([rec] * 70)
+    qs[1::2, 1] ^= np.uint64(1 << 5)
+    k = np.array([1, 30, 9000, 20_000, 100_000] * 14, dtype=np.uint32)
+    masks = np.array([1, 2, 3] * 24, dtype=np.uint32)[:70]
+    check_batch(words_lib(words), lib, qs, k, masks, path, "identical rows")
+
+
+def words_lib(words):
+    class W:
+        pass
+    w = W()
+    w.words = words
+    return w
+
+
+def test_determinism(small):
+    lib_np, lib = small
+    qs = fpsynth.batch_queries(lib_np, 256, 21).words
+    k, masks = fpsynth.uneven_params(256, 22)
+    outs = []
+    for path in PATHS:
+        lib.set_path(path)
+        for _ in range(4):
+            h, off = lib.search_batch(qs, k, masks)
+            outs.append(h.tobytes() + off.tobytes())
+    lib.set_path(fps.PATH_AUTO)
+    assert all(o == outs[0] for o in outs)
+
+
+def test_errors(small):
+    lib_np, lib = small
+    q = lib_np.words[5].copy()
+    bad = q.copy()
+    bad[0] |= np.uint64(1)
+    with pytest.raises(fps.FPSError) as e:
+        lib.search(bad, 30)
+    assert e.value.status == fps.FPS_E_FINGERPRINT
+    bad = q.copy()
+    bad[2] |= np.uint64(1) << np.uint64(40)
+    with pytest.raises(fps.FPSError) as e:
+        lib.search_batch(np.stack([q, bad]), 30)
+    assert e.value.status == fps.FPS_E_FINGERPRINT and "query 1" in str(e.value)
+    with pytest.raises(fps.FPSError) as e:
+        lib.search(q, 30, mask=0)
+    assert e.value.status == fps.FPS_E_ARG
+    with pytest.raises(fps.FPSError) as e:
+        lib.search(q, 30, mask=0b1000)
+    assert e.value.status == fps.FPS_E_ARG
+    # a workspace that is too small
+    import ctypes
+    c = fps.load_library()
+    ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    out = np.empty(30, dtype=fps.HIT_DTYPE)
+    n = ctypes.c_uint32()
+    rc = c.fps_search(lib.handle, ctypes.c_void_p(q.ctypes.data), 30, fps.MASK_ALL,
+                      ctypes.c_void_p(ws.data_ptr()), 1024, ctypes.c_void_p(out.ctypes.data),
+                      ctypes.byref(n), None)
+    assert rc == fps.FPS_E_NOMEM
+    # the handle still works afterwards
+    assert np.array_equal(lib.search(q, 30), oracle.search(lib_np.words, q, 30))
+
+
+def test_server_alone_vs_mix(small):
+    """Each request's answer is the same alone, in a mix and from the oracle."""
+    lib_np, lib = small
+    rng = np.random.default_rng(5)
+    reqs = []
+    for r in range(40):
+        nq = int(rng.integers(1, 65))
+        qs = fpsynth.batch_queries(lib_np, nq, 5000 + r).words
+        k = int(rng.choice([30, 100, 1000]))
+        m = int(rng.choice([1, 3, 7]))
+        reqs.append((qs, k, m))
+    srv = fps.Server(lib, pool_bytes=512 << 20, max_batch_queries=512, n_streams=3)
+    try:
+        tickets = [srv.submit(qs, k, m, deadline_us=10_000) for qs, k, m in reqs]
+        mixed = [srv.wait(t, len(r[0]), r[1]) for t, r in zip(tickets, reqs)]
+        st = srv.stats()
+        assert st["requests"] == 40
+        for (qs, k, m), (h, off, rs) in zip(reqs, mixed):
+            alone, aoff = lib.search_batch(qs, k, np.full(len(qs), m, dtype=np.uint32))
+            want, woff = oracle.search_batch(lib_np.words, qs, k, lib.strides,
+                                             np.full(len(qs), m, dtype=np.uint32))
+            assert np.array_equal(off, woff) and np.array_equal(h, want)
+            assert np.array_equal(aoff, woff) and np.array_equal(alone, want)
+        assert max(r[2]["batch_queries"] for r in mixed) > 64  # requests were coalesced
+    finally:
+        srv.close()
