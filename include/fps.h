@@ -80,9 +80,9 @@ typedef enum {
 /* Library (Fig. 3 step 1: the library file becomes the matrix A).           */
 /* ------------------------------------------------------------------------ */
 
-/* Device bytes needed to hold n records: 24 bytes per record, n rounded up to
- * a multiple of 4096 (word-major layout: all first words, then all second
- * words, then all third words). */
+/* Device bytes needed to hold n records: 21 bytes per record (the 166 keys
+ * packed into one 64-bit, one 64-bit, one 32-bit and one 8-bit word-major
+ * array), n rounded up to a multiple of 4096. */
 size_t fps_library_device_bytes(uint64_t n);
 
 /*
@@ -115,6 +115,12 @@ fps_status fps_library_free(fps_library *lib);
 
 /* Selects the batch scan kernel (default FPS_PATH_AUTO). */
 fps_status fps_set_path(fps_library *lib, fps_path path);
+
+/* Selects the tile shape of the matrix-core kernel: 0 = 64 queries per wave,
+ * 1 = 64 per wave with two waves per SIMD, 2 = 128 per wave, 3 = 32 per wave
+ * with two waves per SIMD; -1 (default) lets the autotuner choose.  Results
+ * never depend on it.  Errors: FPS_E_ARG. */
+fps_status fps_set_variant(fps_library *lib, int variant);
 
 /* ------------------------------------------------------------------------ */
 /* Search (Fig. 3 steps 2-6; single and batch searches of Section 4.4).       */
@@ -185,13 +191,16 @@ fps_status fps_last_search_stats(const fps_library *lib, fps_search_stats *stats
 /*
  * candidate_scale: multiplies every query's candidate-buffer capacity (1.0 is
  *   the default; tiny values force the overflow fallback).
- * sample_records:  records per query used to derive the distance bound (0 =
- *   default 2^20).
+ * sample_records:  records per query whose distance histogram gives the first
+ *   bound (0 = default 2^16).
+ * phase_records:   records per query scanned before the bound is refined from
+ *   the candidates found so far (0 = default 2^22).
  * force_fallback:  nonzero answers every query with the exact two-pass path.
- * These change workspace sizes: query fps_workspace_bytes after setting them.
+ * Results never depend on these; workspace sizes do: query
+ * fps_workspace_bytes after setting them.
  */
 fps_status fps_set_tuning(fps_library *lib, double candidate_scale, uint64_t sample_records,
-                          int force_fallback);
+                          uint64_t phase_records, int force_fallback);
 
 /* ------------------------------------------------------------------------ */
 /* Serving: continuous batching of independent requests (the queue between the */

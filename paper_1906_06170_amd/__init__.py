@@ -74,6 +74,7 @@ EXPORTS = {
                                         ctypes.c_void_p]),
     "fps_library_free": (ctypes.c_int, [ctypes.c_void_p]),
     "fps_set_path": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "fps_set_variant": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "fps_workspace_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_void_p]),
     "fps_search": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
@@ -85,7 +86,7 @@ EXPORTS = {
                                         ctypes.c_void_p, ctypes.c_void_p]),
     "fps_last_search_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "fps_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_uint64,
-                                      ctypes.c_int]),
+                                      ctypes.c_uint64, ctypes.c_int]),
     "fps_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_size_t, ctypes.c_void_p]),
     "fps_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
@@ -165,6 +166,7 @@ class Library:
         nbytes = int(c.fps_library_device_bytes(self.n))
         self._buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         self._ws = None
+        self._ws_sizes = {}
         self._handle = ctypes.c_void_p()
         if strides is None:
             st, ns = None, 0
@@ -215,10 +217,17 @@ class Library:
     def set_path(self, path: int):
         _check(load_library().fps_set_path(self._handle, int(path)))
 
+    def set_variant(self, variant: int):
+        """Matrix-core tile shape (0..3, or -1 for the tuner's choice)."""
+        _check(load_library().fps_set_variant(self._handle, int(variant)))
+
     def set_tuning(self, candidate_scale: float = 1.0, sample_records: int = 0,
-                   force_fallback: bool = False):
+                   phase_records: int = 0, force_fallback: bool = False):
+        """Capacity / bound-sample / phase knobs (results never depend on them)."""
+        self._ws_sizes = {}
         _check(load_library().fps_set_tuning(self._handle, float(candidate_scale),
-                                             int(sample_records), int(bool(force_fallback))))
+                                             int(sample_records), int(phase_records),
+                                             int(bool(force_fallback))))
 
     def last_stats(self) -> dict:
         st = SearchStats()
@@ -231,12 +240,16 @@ class Library:
     def search(self, query, k: int, mask: int = MASK_ALL, stream=None) -> np.ndarray:
         """Top-k of one query: structured array (index, distance), ascending."""
         q = np.ascontiguousarray(np.asarray(query, dtype=np.uint64).reshape(3))
-        kk = np.array([k], dtype=np.uint32)
-        mm = np.array([mask], dtype=np.uint32)
-        nb = ctypes.c_size_t()
-        _check(load_library().fps_workspace_bytes(self._handle, 1, _ptr(kk), _ptr(mm),
-                                                  ctypes.byref(nb)))
-        ws = self._workspace(int(nb.value))
+        key = (int(k), int(mask))
+        nb = self._ws_sizes.get(key)
+        if nb is None:
+            kk = np.array([k], dtype=np.uint32)
+            mm = np.array([mask], dtype=np.uint32)
+            c = ctypes.c_size_t()
+            _check(load_library().fps_workspace_bytes(self._handle, 1, _ptr(kk), _ptr(mm),
+                                                      ctypes.byref(c)))
+            nb = self._ws_sizes[key] = int(c.value)
+        ws = self._workspace(nb)
         out = np.empty(max(int(k), 1), dtype=HIT_DTYPE)
         nout = ctypes.c_uint32()
         _check(load_library().fps_search(self._handle, _ptr(q), int(k), int(mask),

@@ -1,9 +1,15 @@
 // Internal declarations of the MI355X fingerprint top-k engine: device-side
 // parameter blocks and the host launchers of the kernels.
 //
-// Library layout in HBM (word-major): w0[Np], w1[Np], w2[Np] (uint64), Np = n
-// rounded up to a multiple of 4096.  Key j (1..166) of record i is bit (j & 63)
-// of w{j >> 6}[i].  Records [n, Np) are zero and never reported.
+// Library layout in HBM: four word-major arrays, 21 bytes per record (the 166
+// keys need 20.75), Np = n rounded up to a multiple of 4096:
+//   a[Np] uint64: keys 1..63 at bits 1..63, key 160 at bit 0
+//   b[Np] uint64: keys 64..127 at bits 0..63
+//   c[Np] uint32: keys 128..159 at bits 0..31
+//   d[Np] uint8 : keys 161..166 at bits 0..5
+// This only relabels key positions, so the number of differing keys (the
+// distance) is the popcount of a^a' + b^b' + c^c' + d^d'.  Queries are relabeled
+// the same way on the host.  Records [n, Np) are zero and never reported.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>
@@ -16,9 +22,18 @@ namespace fps {
 constexpr int kKeys = 166;
 constexpr int kBins = 168;          // distances 0..166, padded
 constexpr uint64_t kRowAlign = 4096;
+constexpr uint64_t kBytesPerRecord = 21;
 constexpr uint32_t kSortCap = 8192; // candidates with d <= D_k sorted in LDS by one block
 constexpr int kFbBlocks = 2048;     // fallback grid (blocks of 256 threads)
 constexpr int kFbWaves = kFbBlocks * 4;
+
+constexpr int kScanTile = 512;      // records per wave iteration of the single-query scan
+constexpr int kBatchTile = 2048;    // records per work item of the batched kernels
+constexpr int kBoundChunk = 1024;   // records per block of the bound kernel
+constexpr int kHistCopies = 8;      // bound histograms are spread over 8 copies per query
+constexpr uint64_t kDefaultBoundSample = 1ull << 16;  // records of the bound sample
+constexpr uint64_t kDefaultPhaseA = 0;  // first phase length in records (0 = from the schedule)
+constexpr int kMaxPhases = 12;          // scan phases (the bound is refined between phases)
 
 // A union of record ranges (the strides one mask selects), in ascending order,
 // adjacent strides merged.  Virtual index v in [0, neff) enumerates its records
@@ -34,12 +49,10 @@ struct RangeSet {
   uint64_t tboff[FPS_MAX_STRIDES + 1]; // first batch tile of range r (kBatchTile records)
 };
 
-constexpr int kScanTile = 512;      // records per wave iteration of the single-query scan
-constexpr int kBatchTile = 2048;    // records per work item of the batched kernels
-
-// Per-query parameters, uploaded with every call.
+// Per-query parameters, uploaded with every call (query in the library layout).
 struct QueryInfo {
-  uint64_t w[3];
+  uint64_t qa, qb;
+  uint32_t qc, qd;
   uint32_t keff;      // min(k, neff)
   uint32_t rset;      // RangeSet index
   uint64_t cand_off;  // first candidate slot
@@ -54,22 +67,21 @@ struct QBlock {
   uint32_t first;  // position in perm[]
   uint32_t count;  // queries in the block
   uint32_t rset;
-  uint32_t pad;
+  uint32_t tiles;  // batch tiles of the block's range
 };
 
-// Work item of the batched kernels: a query block x one tile of its RangeSet.
-// Items are enumerated implicitly: item = qb_item_off[qb] + tile.
 struct Workspace {
   RangeSet *rsets;
   QueryInfo *qinfo;
   uint32_t *perm;
   QBlock *qblocks;      // for the batched kernels
-  uint64_t *qb_item_off;// nqb + 1 prefix of work items
-  QBlock *bblocks;      // for the bound kernel (<= 32 queries each)
-  uint32_t *T;          // per-query distance bound
+  uint64_t *qb_item;    // per phase: nqb + 1 prefix of work items (tiles of the phase)
+  QBlock *bblocks;      // for the bound kernel (<= kBoundQBlock queries each)
+  uint32_t *bdone;      // per bound block: finished chunk blocks
+  uint32_t *T;          // per-query distance bound (int32; -1 = no candidate wanted)
   uint32_t *count;      // per-query candidates appended (exact even past cap)
   uint32_t *flags;      // per-query: 1 overflow, 2 too many ties for LDS sort, 4 bound failed
-  uint32_t *hist;       // per-query kBins histogram of the bound sample
+  uint32_t *hist;       // per query: kHistCopies x kBins histogram of the bound sample
   uint64_t *cand;       // candidates: (distance << 32) | index
   fps_hit *out;         // results, query q at qinfo[q].out_off
   uint32_t *fb_wave_hist; // fallback: kFbWaves x kBins
@@ -78,28 +90,36 @@ struct Workspace {
 };
 
 struct Lib {
-  const uint64_t *w0, *w1, *w2;
+  const uint64_t *a, *b;
+  const uint32_t *c;
+  const uint8_t *d;
   uint64_t n, np;
 };
 
 // ---- launchers (kernels.hip) ----
-void launch_prep(const Workspace &ws, uint32_t q, hipStream_t s);
+void launch_prep(const Workspace &ws, uint32_t q, uint32_t nbblocks, hipStream_t s);
 void launch_bound(const Lib &lib, const Workspace &ws, uint32_t nbblocks, uint64_t max_sample,
                   hipStream_t s);
-void launch_threshold(const Workspace &ws, uint32_t q, hipStream_t s);
-void launch_scan_single(const Lib &lib, const Workspace &ws, uint32_t qidx, uint64_t tiles,
-                        int cus, hipStream_t s);
-void launch_scan_popcount(const Lib &lib, const Workspace &ws, uint32_t nqb, uint64_t items,
-                          int cus, hipStream_t s);
+void launch_refine(const Workspace &ws, uint32_t q, hipStream_t s);
+void launch_scan_single(const Lib &lib, const Workspace &ws, uint32_t qidx, uint64_t t_begin,
+                        uint64_t t_end, int cus, hipStream_t s);
+// Batched scans: work items are the tiles [tile_lo, tile_hi) of every query
+// block's range (clamped to its tile count); item_off is the phase's nqb + 1
+// prefix of items per query block.
+void launch_scan_popcount(const Lib &lib, const Workspace &ws, uint32_t nqb,
+                          const uint64_t *item_off, uint64_t tile_lo, uint64_t items, int cus,
+                          hipStream_t s);
 void launch_select(const Workspace &ws, uint32_t q, hipStream_t s);
 void launch_fallback(const Lib &lib, const Workspace &ws, uint32_t qidx, uint64_t neff,
                      hipStream_t s);
 // ---- launchers (mfma.hip) ----
-void launch_scan_mfma_i8(const Lib &lib, const Workspace &ws, uint32_t nqb, uint64_t items,
-                         int cus, hipStream_t s);
+void launch_scan_mfma_i8(const Lib &lib, const Workspace &ws, uint32_t nqb,
+                         const uint64_t *item_off, uint64_t tile_lo, uint64_t items, int cus,
+                         int variant, hipStream_t s);
+int mfma_variants();
+uint32_t mfma_qblock(int variant);
 
 constexpr int kPopQBlock = 128;   // queries per block of the popcount kernel
-constexpr int kMfmaQBlock = 256;  // queries per block of the int8 MFMA kernel
 constexpr int kBoundQBlock = 32;  // queries per block of the bound kernel
 
 }  // namespace fps

@@ -3,14 +3,18 @@
 // The search of FPScreen (Fig. 3) computes, for every library row, the
 // Manhattan distance of Section 4.3 to the query and keeps the N smallest.  On
 // 0/1 keys that distance is the number of differing keys, so one record costs
-// three XORs and six 32-bit popcounts.  Top-N is exact and single-pass over the
-// library:
-//   1. bound:  a histogram of the distances of the first S records of each
-//      query's range gives T = the k-th smallest of them, an upper bound of the
-//      k-th smallest over the whole range;
-//   2. scan:   every record with d <= T is appended to the query's candidate
-//      buffer (wave-aggregated: one atomic per wave that has hits);
-//   3. select: a 167-bin histogram of the candidates gives D_k; the candidates
+// six XORs and six 32-bit popcounts over its four words.  Top-N is exact and
+// reads the library once:
+//   1. bound:  a histogram of the distances of the first S1 records of each
+//      query's range gives T1 = the k-th smallest of them; any k records bound
+//      the k-th smallest distance of the whole range from above;
+//   2. scan, in phases of geometrically growing length: every record with
+//      d <= T is appended to the query's candidate buffer (wave-aggregated:
+//      one atomic per wave that has hits);
+//   3. refine, between phases: the candidates hold every record of the prefix
+//      scanned so far with d <= T, so their histogram gives the k-th smallest
+//      distance of that prefix, a tighter bound for the next phase;
+//   4. select: a 167-bin histogram of the candidates gives D_k; the candidates
 //      with d <= D_k are sorted by (d, index) in LDS and the first k are kept.
 // A query whose candidates overflow their buffer, or whose ties at D_k exceed
 // the LDS sort, is answered by an exact two-pass ordered fallback.
@@ -33,9 +37,24 @@ __device__ __forceinline__ uint64_t v2g(const RangeSet *rs, uint64_t v) {
   return rs->begin[r] + (v - rs->voff[r]);
 }
 
-__device__ __forceinline__ uint32_t dist3(uint64_t a, uint64_t b, uint64_t c, uint64_t q0,
-                                          uint64_t q1, uint64_t q2) {
-  return (uint32_t)(__popcll(a ^ q0) + __popcll(b ^ q1) + __popcll(c ^ q2));
+// One record in the library layout (see fps_internal.h).
+struct Rec {
+  uint64_t a, b;
+  uint32_t c, d;
+};
+
+__device__ __forceinline__ Rec load_rec(const Lib &L, uint64_t g) {
+  return Rec{L.a[g], L.b[g], L.c[g], (uint32_t)L.d[g]};
+}
+
+// Number of differing keys: popcount of the XOR of the four words.
+__device__ __forceinline__ uint32_t dist4(uint64_t a, uint64_t b, uint32_t c, uint32_t d,
+                                          uint64_t qa, uint64_t qb, uint32_t qc, uint32_t qd) {
+  return (uint32_t)(__popcll(a ^ qa) + __popcll(b ^ qb) + __popc(c ^ qc) + __popc(d ^ qd));
+}
+
+__device__ __forceinline__ uint32_t dist_rec(const Rec &r, const QueryInfo *q) {
+  return dist4(r.a, r.b, r.c, r.d, q->qa, q->qb, q->qc, q->qd);
 }
 
 // Appends key for every lane with hit set: one atomic per wave.
@@ -58,101 +77,156 @@ __device__ __forceinline__ void wave_append(bool hit, uint64_t key, uint32_t *cn
 // Clears the per-query counters and histograms (a fill kernel, so the sequence
 // can be captured into a graph).
 // ---------------------------------------------------------------------------
-__global__ void k_prep(Workspace ws, uint32_t q) {
+__global__ void k_prep(Workspace ws, uint32_t q, uint32_t nbblocks) {
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < q; i += stride) {
     ws.count[i] = 0;
     ws.flags[i] = 0;
-    ws.T[i] = (uint32_t)kKeys;
+    ws.T[i] = 0xFFFFFFFFu;
   }
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < q * kBins; i += stride)
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nbblocks; i += stride)
+    ws.bdone[i] = 0;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < q * kHistCopies * kBins;
+       i += stride)
     ws.hist[i] = 0;
 }
 
-void launch_prep(const Workspace &ws, uint32_t q, hipStream_t s) {
-  uint32_t blocks = (q * kBins + 255) / 256;
+void launch_prep(const Workspace &ws, uint32_t q, uint32_t nbblocks, hipStream_t s) {
+  uint32_t blocks = (q * kHistCopies * kBins + 255) / 256;
   if (blocks > 1024) blocks = 1024;
   if (blocks == 0) blocks = 1;
-  hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(256), 0, s, ws, q);
+  hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(256), 0, s, ws, q, nbblocks);
 }
 
 // ---------------------------------------------------------------------------
 // Bound: distance histogram of the first `sample` records of each query's
-// range.  Grid: x = sample chunk, y = block of <= 32 queries sharing a range.
+// range.  Grid: x = 1024-record chunk, y = block of <= 32 queries sharing a
+// range.  Blocks add their histograms into one of 8 copies per query (spreading
+// the atomics); the last chunk block of a query block to finish sums the copies
+// and sets T1 = smallest t whose cumulative sample count reaches keff (166 when
+// the sample holds fewer than keff records, so every record passes).
 // ---------------------------------------------------------------------------
-constexpr int kBoundChunk = 8192;
-
 __global__ __launch_bounds__(256) void k_bound(Lib lib, Workspace ws) {
   __shared__ uint32_t h[kBoundQBlock * kBins];
-  __shared__ uint64_t qw[kBoundQBlock][3];
+  __shared__ QueryInfo qs[kBoundQBlock];
+  __shared__ uint32_t s_last;
   const QBlock bb = ws.bblocks[blockIdx.y];
   const RangeSet *rs = ws.rsets + bb.rset;
   const uint64_t sample = ws.qinfo[ws.perm[bb.first]].sample;
   const uint64_t v0 = (uint64_t)blockIdx.x * kBoundChunk;
-  if (v0 >= sample) return;  // whole block
-  const uint64_t v1 = min(v0 + (uint64_t)kBoundChunk, sample);
-  for (uint32_t i = threadIdx.x; i < bb.count * kBins; i += blockDim.x) h[i] = 0;
-  for (uint32_t i = threadIdx.x; i < bb.count * 3; i += blockDim.x)
-    qw[i / 3][i % 3] = ws.qinfo[ws.perm[bb.first + i / 3]].w[i % 3];
-  __syncthreads();
-  for (uint64_t v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
-    const uint64_t g = v2g(rs, v);
-    const uint64_t a = lib.w0[g], b = lib.w1[g], c = lib.w2[g];
-    for (uint32_t j = 0; j < bb.count; ++j) {
-      const uint32_t d = dist3(a, b, c, qw[j][0], qw[j][1], qw[j][2]);
-      atomicAdd(&h[j * kBins + d], 1u);
+  const uint32_t tid = threadIdx.x;
+  const uint32_t copy = blockIdx.x % kHistCopies;
+  if (v0 < sample) {
+    const uint64_t v1 = min(v0 + (uint64_t)kBoundChunk, sample);
+    for (uint32_t i = tid; i < bb.count * kBins; i += blockDim.x) h[i] = 0;
+    for (uint32_t i = tid; i < bb.count; i += blockDim.x) qs[i] = ws.qinfo[ws.perm[bb.first + i]];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kBoundChunk / 256; ++u) {
+      const uint64_t v = v0 + 256 * u + tid;
+      if (v < v1) {
+        const Rec r = load_rec(lib, v2g(rs, v));
+        for (uint32_t j = 0; j < bb.count; ++j) atomicAdd(&h[j * kBins + dist_rec(r, &qs[j])], 1u);
+      }
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < bb.count * kBins; i += blockDim.x) {
+      const uint32_t x = h[i];
+      if (x)
+        atomicAdd(&ws.hist[((uint64_t)ws.perm[bb.first + i / kBins] * kHistCopies + copy) * kBins +
+                           i % kBins],
+                  x);
     }
   }
+  __threadfence();
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < bb.count * kBins; i += blockDim.x) {
-    const uint32_t x = h[i];
-    if (x) atomicAdd(&ws.hist[(uint64_t)ws.perm[bb.first + i / kBins] * kBins + i % kBins], x);
+  if (tid == 0) s_last = atomicAdd(&ws.bdone[blockIdx.y], 1u) == gridDim.x - 1 ? 1u : 0u;
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  for (uint32_t i = tid; i < bb.count * kBins; i += blockDim.x) {
+    const uint32_t *src = ws.hist + (uint64_t)ws.perm[bb.first + i / kBins] * kHistCopies * kBins;
+    uint32_t x = 0;
+#pragma unroll
+    for (int c = 0; c < kHistCopies; ++c)
+      x += __hip_atomic_load(src + c * kBins + i % kBins, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    h[i] = x;
   }
-}
-
-void launch_bound(const Lib &lib, const Workspace &ws, uint32_t nbblocks, uint64_t max_sample,
-                  hipStream_t s) {
-  if (nbblocks == 0 || max_sample == 0) return;
-  const uint32_t chunks = (uint32_t)((max_sample + kBoundChunk - 1) / kBoundChunk);
-  hipLaunchKernelGGL(k_bound, dim3(chunks, nbblocks), dim3(256), 0, s, lib, ws);
-}
-
-// T = smallest t whose cumulative sample count reaches keff.  keff = 0 gives
-// T = -1 (no candidate can pass); a sample too small to hold keff records gives
-// T = 166 (every record passes).
-__global__ void k_threshold(Workspace ws, uint32_t q) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= q) return;
-  const uint32_t keff = ws.qinfo[i].keff;
-  uint32_t T = (uint32_t)kKeys;
-  if (keff == 0) {
-    T = 0xFFFFFFFFu;
-  } else {
-    uint64_t cum = 0;
+  __syncthreads();
+  for (uint32_t j = tid; j < bb.count; j += blockDim.x) {
+    const uint32_t q = ws.perm[bb.first + j];
+    const uint32_t keff = ws.qinfo[q].keff;
+    uint32_t T = (uint32_t)kKeys, cum = 0;
     for (uint32_t t = 0; t <= (uint32_t)kKeys; ++t) {
-      cum += ws.hist[(uint64_t)i * kBins + t];
+      cum += h[j * kBins + t];
       if (cum >= keff) {
         T = t;
         break;
       }
     }
+    ws.T[q] = T;
   }
-  ws.T[i] = T;
 }
 
-void launch_threshold(const Workspace &ws, uint32_t q, hipStream_t s) {
-  hipLaunchKernelGGL(k_threshold, dim3((q + 255) / 256), dim3(256), 0, s, ws, q);
+void launch_bound(const Lib &lib, const Workspace &ws, uint32_t nbblocks, uint64_t max_sample,
+                  hipStream_t s) {
+  if (nbblocks == 0) return;
+  uint32_t chunks = (uint32_t)((max_sample + kBoundChunk - 1) / kBoundChunk);
+  if (chunks == 0) chunks = 1;
+  hipLaunchKernelGGL(k_bound, dim3(chunks, nbblocks), dim3(256), 0, s, lib, ws);
 }
 
 // ---------------------------------------------------------------------------
-// Single-query scan: HBM-bound stream over the query's ranges.  A wave covers
-// a 512-record tile per iteration: every lane loads two consecutive records of
-// each word array with one 16-byte load (4 x 3 loads in flight per lane).
+// Refine: after a scan phase the candidate buffer holds every record of the
+// prefix scanned so far with d <= T (each phase appended d <= the bound of its
+// time, and bounds only shrink); the keff-th smallest of them is a tighter
+// bound.  One block per query.  A query whose buffer overflowed keeps its bound
+// (it is answered by the fallback anyway).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_refine(Workspace ws) {
+  __shared__ uint32_t hist[kBins];
+  const uint32_t q = blockIdx.x, tid = threadIdx.x;
+  const QueryInfo *qi = ws.qinfo + q;
+  const uint32_t keff = qi->keff;
+  if (keff == 0) return;
+  const uint32_t n = ws.count[q];
+  if (n > qi->cap) return;
+  const uint64_t *cand = ws.cand + qi->cand_off;
+  for (uint32_t i = tid; i < kBins; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  for (uint32_t i = tid; i < n; i += blockDim.x) atomicAdd(&hist[(uint32_t)(cand[i] >> 32)], 1u);
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t cum = 0;
+    const int32_t T1 = (int32_t)ws.T[q];
+    for (int32_t t = 0; t < T1; ++t) {
+      cum += hist[t];
+      if (cum >= keff) {
+        ws.T[q] = (uint32_t)t;
+        break;
+      }
+    }
+  }
+}
+
+void launch_refine(const Workspace &ws, uint32_t q, hipStream_t s) {
+  if (q == 0) return;
+  hipLaunchKernelGGL(k_refine, dim3(q), dim3(256), 0, s, ws);
+}
+
+// ---------------------------------------------------------------------------
+// Single-query scan: HBM-bound stream over the query's ranges.  A wave covers a
+// 512-record tile per iteration in four groups of 128 records; in each group a
+// lane takes two consecutive records, so every load instruction of the wave
+// reads one contiguous segment (16-byte loads of a and b, 8-byte of c, 2-byte
+// of d): 16 loads, 168 bytes per lane in flight.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_scan_single(Lib lib, Workspace ws, uint32_t qidx,
-                                                     uint64_t tiles) {
+                                                     uint64_t t_begin, uint64_t t_end) {
   const QueryInfo *qi = ws.qinfo + qidx;
-  const uint64_t q0 = qi->w[0], q1 = qi->w[1], q2 = qi->w[2];
+  const uint64_t qa = qi->qa, qb = qi->qb;
+  const uint32_t qc = qi->qc, qd = qi->qd;
   const int32_t T = (int32_t)ws.T[qidx];
   const RangeSet *rs = ws.rsets + qi->rset;
   uint32_t *cnt = ws.count + qidx;
@@ -162,23 +236,26 @@ __global__ __launch_bounds__(256) void k_scan_single(Lib lib, Workspace ws, uint
   const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
   uint32_t r = 0;
-  for (uint64_t t = wave; t < tiles; t += nwaves) {
+  for (uint64_t t = t_begin + wave; t < t_end; t += nwaves) {
     while (t >= rs->t1off[r + 1]) ++r;
     const uint64_t rb = rs->begin[r], re = rs->end[r];
     const uint64_t base = (rb & ~(uint64_t)(kScanTile - 1)) + (t - rs->t1off[r]) * kScanTile;
-    ulonglong2 a[4], b[4], c[4];
+    ulonglong2 A[4], B[4];
+    uint2 C[4];
+    uint32_t D[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const uint64_t i = base + 128 * u + 2 * lane;
-      a[u] = *reinterpret_cast<const ulonglong2 *>(lib.w0 + i);
-      b[u] = *reinterpret_cast<const ulonglong2 *>(lib.w1 + i);
-      c[u] = *reinterpret_cast<const ulonglong2 *>(lib.w2 + i);
+      A[u] = *reinterpret_cast<const ulonglong2 *>(lib.a + i);
+      B[u] = *reinterpret_cast<const ulonglong2 *>(lib.b + i);
+      C[u] = *reinterpret_cast<const uint2 *>(lib.c + i);
+      D[u] = *reinterpret_cast<const uint16_t *>(lib.d + i);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const uint64_t i = base + 128 * u + 2 * lane;
-      const int32_t d0 = (int32_t)dist3(a[u].x, b[u].x, c[u].x, q0, q1, q2);
-      const int32_t d1 = (int32_t)dist3(a[u].y, b[u].y, c[u].y, q0, q1, q2);
+      const int32_t d0 = (int32_t)dist4(A[u].x, B[u].x, C[u].x, D[u] & 0xFFu, qa, qb, qc, qd);
+      const int32_t d1 = (int32_t)dist4(A[u].y, B[u].y, C[u].y, D[u] >> 8, qa, qb, qc, qd);
       const bool h0 = d0 <= T && i >= rb && i < re;
       const bool h1 = d1 <= T && i + 1 >= rb && i + 1 < re;
       wave_append(h0, ((uint64_t)d0 << 32) | i, cnt, cand, cap);
@@ -187,14 +264,14 @@ __global__ __launch_bounds__(256) void k_scan_single(Lib lib, Workspace ws, uint
   }
 }
 
-void launch_scan_single(const Lib &lib, const Workspace &ws, uint32_t qidx, uint64_t tiles,
-                        int cus, hipStream_t s) {
-  if (tiles == 0) return;
-  uint64_t blocks = (tiles + 3) / 4;  // 4 waves per block
+void launch_scan_single(const Lib &lib, const Workspace &ws, uint32_t qidx, uint64_t t_begin,
+                        uint64_t t_end, int cus, hipStream_t s) {
+  if (t_end <= t_begin) return;
+  uint64_t blocks = (t_end - t_begin + 3) / 4;  // 4 waves per block
   const uint64_t maxb = (uint64_t)cus * 8;
   if (blocks > maxb) blocks = maxb;
   hipLaunchKernelGGL(k_scan_single, dim3((uint32_t)blocks), dim3(256), 0, s, lib, ws, qidx,
-                     tiles);
+                     t_begin, t_end);
 }
 
 // ---------------------------------------------------------------------------
@@ -206,15 +283,17 @@ void launch_scan_single(const Lib &lib, const Workspace &ws, uint32_t qidx, uint
 constexpr int kPopRL = 4;
 
 __global__ __launch_bounds__(256) void k_scan_popcount(Lib lib, Workspace ws, uint32_t nqb,
-                                                       uint64_t items) {
-  __shared__ uint64_t qw[kPopQBlock][4];  // w0, w1, w2, -(T+1)
+                                                       const uint64_t *item_off,
+                                                       uint64_t tile_lo, uint64_t items) {
+  __shared__ uint64_t qw[kPopQBlock][3];  // a, b, c | d << 32
+  __shared__ int32_t qseed[kPopQBlock];   // -(T+1)
   __shared__ uint32_t qid[kPopQBlock];
   uint32_t cur_qb = 0xFFFFFFFFu;
   QBlock qb{};
   const uint32_t tid = threadIdx.x;
   for (uint64_t item = blockIdx.x; item < items; item += gridDim.x) {
     uint32_t b = 0;
-    while (b + 1 < nqb && item >= ws.qb_item_off[b + 1]) ++b;
+    while (b + 1 < nqb && item >= item_off[b + 1]) ++b;
     if (b != cur_qb) {
       __syncthreads();
       cur_qb = b;
@@ -222,39 +301,37 @@ __global__ __launch_bounds__(256) void k_scan_popcount(Lib lib, Workspace ws, ui
       for (uint32_t j = tid; j < qb.count; j += blockDim.x) {
         const uint32_t q = ws.perm[qb.first + j];
         qid[j] = q;
-        qw[j][0] = ws.qinfo[q].w[0];
-        qw[j][1] = ws.qinfo[q].w[1];
-        qw[j][2] = ws.qinfo[q].w[2];
-        qw[j][3] = (uint64_t)(uint32_t)(-((int32_t)ws.T[q] + 1));
+        qw[j][0] = ws.qinfo[q].qa;
+        qw[j][1] = ws.qinfo[q].qb;
+        qw[j][2] = (uint64_t)ws.qinfo[q].qc | ((uint64_t)ws.qinfo[q].qd << 32);
+        qseed[j] = -((int32_t)ws.T[q] + 1);
       }
       __syncthreads();
     }
     const RangeSet *rs = ws.rsets + qb.rset;
-    const uint64_t tile = item - ws.qb_item_off[b];
+    const uint64_t tile = item - item_off[b] + min(tile_lo, (uint64_t)qb.tiles);
     uint32_t r = 0;
     while (tile >= rs->tboff[r + 1]) ++r;
     const uint64_t g0 = rs->begin[r] + (tile - rs->tboff[r]) * kBatchTile;
     const uint64_t g1 = min(g0 + (uint64_t)kBatchTile, rs->end[r]);
     for (uint64_t sub = g0; sub < g1; sub += 256 * kPopRL) {
-      uint64_t x0[kPopRL], x1[kPopRL], x2[kPopRL];
+      Rec x[kPopRL];
       bool ok[kPopRL];
 #pragma unroll
       for (int u = 0; u < kPopRL; ++u) {
         const uint64_t g = sub + 256 * u + tid;
         ok[u] = g < g1;
-        const uint64_t gs = ok[u] ? g : g0;
-        x0[u] = lib.w0[gs];
-        x1[u] = lib.w1[gs];
-        x2[u] = lib.w2[gs];
+        x[u] = load_rec(lib, ok[u] ? g : g0);
       }
       for (uint32_t j = 0; j < qb.count; ++j) {
-        const uint64_t q0 = qw[j][0], q1 = qw[j][1], q2 = qw[j][2];
-        const int32_t seed = (int32_t)(uint32_t)qw[j][3];
+        const uint64_t qa = qw[j][0], qb2 = qw[j][1], qcd = qw[j][2];
+        const int32_t seed = qseed[j];
         int32_t v[kPopRL];
         int32_t any = 0;
 #pragma unroll
         for (int u = 0; u < kPopRL; ++u) {
-          v[u] = seed + (int32_t)dist3(x0[u], x1[u], x2[u], q0, q1, q2);
+          v[u] = seed + (int32_t)dist4(x[u].a, x[u].b, x[u].c, x[u].d, qa, qb2, (uint32_t)qcd,
+                                       (uint32_t)(qcd >> 32));
           any |= v[u];
         }
         if (__ballot(any < 0) == 0) continue;
@@ -273,14 +350,15 @@ __global__ __launch_bounds__(256) void k_scan_popcount(Lib lib, Workspace ws, ui
   }
 }
 
-void launch_scan_popcount(const Lib &lib, const Workspace &ws, uint32_t nqb, uint64_t items,
-                          int cus, hipStream_t s) {
+void launch_scan_popcount(const Lib &lib, const Workspace &ws, uint32_t nqb,
+                          const uint64_t *item_off, uint64_t tile_lo, uint64_t items, int cus,
+                          hipStream_t s) {
   if (items == 0) return;
   uint64_t blocks = items;
   const uint64_t maxb = (uint64_t)cus * 8;
   if (blocks > maxb) blocks = maxb;
   hipLaunchKernelGGL(k_scan_popcount, dim3((uint32_t)blocks), dim3(256), 0, s, lib, ws, nqb,
-                     items);
+                     item_off, tile_lo, items);
 }
 
 // ---------------------------------------------------------------------------
@@ -381,7 +459,6 @@ __global__ __launch_bounds__(256) void k_fb_hist(Lib lib, Workspace ws, uint32_t
   __shared__ uint32_t h[4][kBins];
   const QueryInfo *qi = ws.qinfo + qidx;
   const RangeSet *rs = ws.rsets + qi->rset;
-  const uint64_t q0 = qi->w[0], q1 = qi->w[1], q2 = qi->w[2];
   const uint32_t wl = threadIdx.x >> 6, lane = lane_id();
   const uint64_t w = (uint64_t)blockIdx.x * 4 + wl;
   for (uint32_t i = threadIdx.x; i < 4 * kBins; i += blockDim.x) (&h[0][0])[i] = 0;
@@ -389,7 +466,7 @@ __global__ __launch_bounds__(256) void k_fb_hist(Lib lib, Workspace ws, uint32_t
   const uint64_t v0 = w * chunk, v1 = min(v0 + chunk, neff);
   for (uint64_t v = v0 + lane; v < v1; v += 64) {
     const uint64_t g = v2g(rs, v);
-    atomicAdd(&h[wl][dist3(lib.w0[g], lib.w1[g], lib.w2[g], q0, q1, q2)], 1u);
+    atomicAdd(&h[wl][dist_rec(load_rec(lib, g), qi)], 1u);
   }
   __syncthreads();
   for (uint32_t b = lane; b < (uint32_t)kBins; b += 64) ws.fb_wave_hist[w * kBins + b] = h[wl][b];
@@ -423,7 +500,6 @@ __global__ __launch_bounds__(256) void k_fb_emit(Lib lib, Workspace ws, uint32_t
   __shared__ uint32_t s_dk;
   const QueryInfo *qi = ws.qinfo + qidx;
   const RangeSet *rs = ws.rsets + qi->rset;
-  const uint64_t q0 = qi->w[0], q1 = qi->w[1], q2 = qi->w[2];
   const uint32_t keff = qi->keff;
   fps_hit *out = ws.out + qi->out_off;
   const uint32_t wl = threadIdx.x >> 6, lane = lane_id();
@@ -454,7 +530,7 @@ __global__ __launch_bounds__(256) void k_fb_emit(Lib lib, Workspace ws, uint32_t
     bool act = false;
     if (v < v1) {
       g = v2g(rs, v);
-      d = dist3(lib.w0[g], lib.w1[g], lib.w2[g], q0, q1, q2);
+      d = dist_rec(load_rec(lib, g), qi);
       act = d <= dk;
     }
     uint64_t eq = __ballot(act);

@@ -7,10 +7,11 @@
 //     u = d - T_q - 1,
 // whose sign says whether the record is a candidate (d <= T_q).  Everything is
 // folded into one int8 product of K = 192 slots (6 MFMA K-steps of 32):
-//   slot j in 1..166 : query byte -2 * q_j,  record byte r_j        -> -2 q.r
-//   slots 0 and 167  : query bytes c1, c2,   record bytes 1, 1       -> c1 + c2 = |q| - T_q - 1
+//   slots 0..165     : query byte -2 * q_s,  record byte r_s         -> -2 q.r
+//   slots 166, 167   : query bytes c1, c2,   record bytes 1, 1       -> c1 + c2 = |q| - T_q - 1
 //   slots 168, 169   : query bytes 1, 1,     record bytes p1, p2     -> p1 + p2 = |r|
-// (slots 0 and 167..191 carry no key: bit 0 and keys above 166 are always 0).
+// Slot s holds bit s of the record in the library layout (a: slots 0..63,
+// b: 64..127, c: 128..159, d: 160..165); slots 166..191 carry no key.
 // So the epilogue is an OR over the accumulators and one sign test; only tiles
 // holding a candidate take the slow path that decodes (query, record).
 //
@@ -18,10 +19,19 @@
 // term, invalid records (past the end of a tile) get p1 = p2 = 127 and no keys:
 // both make u >= 87, so they can never pass.
 //
-// Layout: 4 waves per block, each holding 2 query tiles of 32 rows (A operands
-// stay in registers, 48 VGPRs); records are expanded from bits to bytes into
-// LDS in stages of 128 (208-byte padded rows, so the 16-byte fragment reads of
-// a wave hit distinct banks) and shared by the 4 waves.
+// Layout: 4 waves per block, each holding MQ query tiles of 32 rows (A operands
+// stay in registers); records are expanded from bits to bytes into LDS in
+// stages of 128 (208-byte padded rows, so the 16-byte fragment reads of a wave
+// hit distinct banks) and shared by the 4 waves.  A block walks its work items
+// as one stream of stages: the records of stage s+2 are loaded into registers
+// while stage s is multiplied, and stage s+1 is expanded into the other LDS
+// buffer, so each stage costs one barrier and HBM latency stays hidden.  The
+// four 32-record columns of a stage are multiplied back to back (fragments of
+// column c+1 are read while column c is in the matrix core) and all results
+// are OR-ed into one flag; only a stage that holds a candidate is multiplied
+// again, column by column, to decode its hits.  In a 32x32 result tile the 32
+// lanes of a half-wave share one query row per accumulator element, so hits
+// are appended with one atomic per half-wave.
 #include "fps_internal.h"
 
 namespace fps {
@@ -29,161 +39,320 @@ namespace fps {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int kMQ = 2;            // 32-row query tiles per wave
-constexpr int kSub = 128;         // records per LDS stage
-constexpr int kRecStride = 208;   // bytes per expanded record (192 + 16 pad)
+constexpr int kSub = 128;                       // records per LDS stage
+constexpr int kSubPerTile = kBatchTile / kSub;  // stages per work item
+constexpr int kRecStride = 208;                 // bytes per expanded record (192 + 16 pad)
 
 // Four key bits -> four bytes of value 0 or 1 (shifted copies do not overlap).
 __device__ __forceinline__ uint32_t spread4(uint32_t nib) {
   return (nib * 0x00204081u) & 0x01010101u;
 }
 
-__device__ __forceinline__ uint32_t chunk32(uint64_t w0, uint64_t w1, uint64_t w2, int c) {
-  const uint64_t w = c < 2 ? w0 : (c < 4 ? w1 : w2);
-  return (c & 1) ? (uint32_t)(w >> 32) : (uint32_t)w;
+// 32-bit chunk i (0..5) of a record: lo a, hi a, lo b, hi b, c, d.
+__device__ __forceinline__ uint32_t chunk32(uint64_t a, uint64_t b, uint32_t c, uint32_t d,
+                                            int i) {
+  switch (i) {
+    case 0: return (uint32_t)a;
+    case 1: return (uint32_t)(a >> 32);
+    case 2: return (uint32_t)b;
+    case 3: return (uint32_t)(b >> 32);
+    case 4: return c;
+    default: return d;
+  }
 }
 
-__global__ __launch_bounds__(256) void k_scan_mfma_i8(Lib lib, Workspace ws, uint32_t nqb,
-                                                      uint64_t items, uint64_t per_block) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[kSub * kRecStride];
-  const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const uint64_t it0 = (uint64_t)blockIdx.x * per_block;
-  const uint64_t it1 = min(it0 + per_block, items);
-  v4i A[kMQ][6];
-  uint32_t cur_qb = 0xFFFFFFFFu;
-  QBlock qb{};
-  bool wave_live = false;
-  for (uint64_t item = it0; item < it1; ++item) {
-    uint32_t b = 0;
-    while (b + 1 < nqb && item >= ws.qb_item_off[b + 1]) ++b;
-    if (b != cur_qb) {
-      cur_qb = b;
-      qb = ws.qblocks[b];
-      wave_live = qb.count > wv * (kMQ * 32);
-      // A operands of this wave: row i = lane & 31 of tile mq; K slice 16 * (lane >> 5).
+// A work item: query block b and the records [t0, t1) of one batch tile.
+struct Item {
+  uint32_t b;
+  uint64_t t0, t1;
+};
+
+// A stage: query block b and the records [g0, g1) (at most kSub, maybe none).
+struct Stage {
+  uint32_t b;
+  uint64_t g0, g1;
+};
+
+__device__ __forceinline__ Item describe(const Workspace &ws, const uint64_t *item_off,
+                                         uint32_t nqb, uint64_t tile_lo, uint64_t item) {
+  uint32_t b = 0;
+  while (b + 1 < nqb && item >= item_off[b + 1]) ++b;
+  const QBlock qb = ws.qblocks[b];
+  const RangeSet *rs = ws.rsets + qb.rset;
+  const uint64_t tile = item - item_off[b] + min(tile_lo, (uint64_t)qb.tiles);
+  uint32_t r = 0;
+  while (tile >= rs->tboff[r + 1]) ++r;
+  Item it;
+  it.b = b;
+  it.t0 = rs->begin[r] + (tile - rs->tboff[r]) * kBatchTile;
+  it.t1 = min(it.t0 + (uint64_t)kBatchTile, rs->end[r]);
+  return it;
+}
+
+__device__ __forceinline__ Stage stage_of(const Item &it, uint32_t sub) {
+  Stage st;
+  st.b = it.b;
+  st.g0 = min(it.t0 + (uint64_t)sub * kSub, it.t1);
+  st.g1 = min(st.g0 + (uint64_t)kSub, it.t1);
+  return st;
+}
+
+// Records of a stage held in registers: thread tid loads record tid >> 1.
+struct Regs {
+  uint64_t a, b;
+  uint32_t c, d;
+  uint32_t ok, pad;
+};
+
+__device__ __forceinline__ Regs load_stage(const Lib &lib, const Stage &st, uint32_t tid) {
+  Regs R;
+  const uint64_t g = st.g0 + (tid >> 1);
+  R.ok = g < st.g1 ? 1u : 0u;
+  R.pad = 0;
+  const uint64_t gs = R.ok ? g : 0;
+  R.a = lib.a[gs];
+  R.b = lib.b[gs];
+  R.c = lib.c[gs];
+  R.d = (uint32_t)lib.d[gs];
+  return R;
+}
+
+// Thread (record tid >> 1, half tid & 1) writes the 96 slots 96h .. 96h + 95.
+__device__ __forceinline__ void expand(const Regs &R, uint8_t *buf, uint32_t tid) {
+  const uint32_t rr = tid >> 1, h = tid & 1;
+  const uint64_t ra = R.ok ? R.a : 0, rb = R.ok ? R.b : 0;
+  const uint32_t rc = R.ok ? R.c : 0, rd = R.ok ? R.d : 0;
+  const uint32_t pr = (uint32_t)(__popcll(ra) + __popcll(rb) + __popc(rc) + __popc(rd));
+  const uint32_t p1 = R.ok ? (pr > 127 ? 127 : pr) : 127;
+  const uint32_t p2 = R.ok ? pr - p1 : 127;
+  const uint32_t ch[3] = {h ? (uint32_t)(rb >> 32) : (uint32_t)ra, h ? rc : (uint32_t)(ra >> 32),
+                          h ? rd : (uint32_t)rb};
+  uint32_t dw[24];
 #pragma unroll
-      for (int mq = 0; mq < kMQ; ++mq) {
-        const uint32_t row = wv * (kMQ * 32) + mq * 32 + (lane & 31);
-        uint64_t q0 = 0, q1 = 0, q2 = 0;
-        int32_t qc = 254;
-        const bool valid = row < qb.count;
-        if (valid) {
-          const uint32_t q = ws.perm[qb.first + row];
-          q0 = ws.qinfo[q].w[0];
-          q1 = ws.qinfo[q].w[1];
-          q2 = ws.qinfo[q].w[2];
-          qc = (int32_t)ws.qinfo[q].popc - (int32_t)ws.T[q] - 1;
-        }
-        const int32_t c1 = qc > 127 ? 127 : (qc < -127 ? -127 : qc);
-        const int32_t c2 = qc - c1;
+  for (int e = 0; e < 24; ++e) dw[e] = spread4((ch[e / 8] >> (4 * (e % 8))) & 15u);
+  if (h == 1) {
+    dw[17] |= (1u << 16) | (1u << 24);  // slots 166, 167
+    dw[18] |= p1 | (p2 << 8);           // slots 168, 169
+  }
+  v4i *dst = reinterpret_cast<v4i *>(buf + rr * kRecStride + 96 * h);
 #pragma unroll
-        for (int s = 0; s < 6; ++s) {
+  for (int e = 0; e < 6; ++e) {
+    v4i v = {(int)dw[4 * e], (int)dw[4 * e + 1], (int)dw[4 * e + 2], (int)dw[4 * e + 3]};
+    dst[e] = v;
+  }
+}
+
+// A operands of wave wv: row i = lane & 31 of tile mq; K slice 16 * (lane >> 5).
+template <int MQ>
+__device__ __forceinline__ void build_a(const Workspace &ws, const QBlock &qb, uint32_t wv,
+                                        uint32_t lane, v4i (&A)[MQ][6]) {
 #pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            const int k0 = 32 * s + 16 * (int)(lane >> 5) + 4 * m;
-            uint32_t x = spread4((chunk32(q0, q1, q2, k0 >> 5) >> (k0 & 31)) & 15u) * 0xFEu;
-            if (k0 == 0) x = (x & 0xFFFFFF00u) | ((uint32_t)c1 & 0xFFu);
-            if (k0 == 164) x = (x & 0x00FFFFFFu) | (((uint32_t)c2 & 0xFFu) << 24);
-            if (k0 == 168 && valid) x = (x & 0xFFFF0000u) | 0x0101u;
-            A[mq][s][m] = (int)x;
-          }
-        }
-      }
+  for (int mq = 0; mq < MQ; ++mq) {
+    const uint32_t row = wv * (MQ * 32) + mq * 32 + (lane & 31);
+    uint64_t qa = 0, qbw = 0;
+    uint32_t qcw = 0, qdw = 0;
+    int32_t qc = 254;
+    const bool valid = row < qb.count;
+    if (valid) {
+      const uint32_t q = ws.perm[qb.first + row];
+      qa = ws.qinfo[q].qa;
+      qbw = ws.qinfo[q].qb;
+      qcw = ws.qinfo[q].qc;
+      qdw = ws.qinfo[q].qd;
+      qc = (int32_t)ws.qinfo[q].popc - (int32_t)ws.T[q] - 1;
     }
-    const RangeSet *rs = ws.rsets + qb.rset;
-    const uint64_t tile = item - ws.qb_item_off[b];
-    uint32_t r = 0;
-    while (tile >= rs->tboff[r + 1]) ++r;
-    const uint64_t g0 = rs->begin[r] + (tile - rs->tboff[r]) * kBatchTile;
-    const uint64_t g1 = min(g0 + (uint64_t)kBatchTile, rs->end[r]);
-    for (uint64_t sub = g0; sub < g1; sub += kSub) {
-      // ---- expand 128 records into LDS: thread = (record tid>>1, half tid&1)
-      {
-        const uint32_t rr = tid >> 1, h = tid & 1;
-        const uint64_t g = sub + rr;
-        const bool ok = g < g1;
-        const uint64_t w0 = ok ? lib.w0[g] : 0, w1 = ok ? lib.w1[g] : 0, w2 = ok ? lib.w2[g] : 0;
-        const uint32_t pr = (uint32_t)(__popcll(w0) + __popcll(w1) + __popcll(w2));
-        const uint32_t p1 = ok ? (pr > 127 ? 127 : pr) : 127;
-        const uint32_t p2 = ok ? pr - p1 : 127;
-        uint32_t dw[24];
+    const int32_t c1 = qc > 127 ? 127 : (qc < -127 ? -127 : qc);
+    const int32_t c2 = qc - c1;
 #pragma unroll
-        for (int e = 0; e < 24; ++e) {
-          const uint32_t ch = chunk32(w0, w1, w2, 3 * (int)h + e / 8);
-          dw[e] = spread4((ch >> (4 * (e % 8))) & 15u);
-        }
-        if (h == 0) {
-          dw[0] |= 1u;                 // slot 0
-        } else {
-          dw[17] |= 1u << 24;          // slot 167
-          dw[18] |= p1 | (p2 << 8);    // slots 168, 169
-        }
-        v4i *dst = reinterpret_cast<v4i *>(lds + rr * kRecStride + 96 * h);
+    for (int s = 0; s < 6; ++s) {
 #pragma unroll
-        for (int e = 0; e < 6; ++e) {
-          v4i v = {(int)dw[4 * e], (int)dw[4 * e + 1], (int)dw[4 * e + 2], (int)dw[4 * e + 3]};
-          dst[e] = v;
-        }
+      for (int m = 0; m < 4; ++m) {
+        const int k0 = 32 * s + 16 * (int)(lane >> 5) + 4 * m;
+        uint32_t x = spread4((chunk32(qa, qbw, qcw, qdw, s) >> (k0 & 31)) & 15u) * 0xFEu;
+        if (k0 == 164)
+          x = (x & 0x0000FFFFu) | (((uint32_t)c1 & 0xFFu) << 16) | (((uint32_t)c2 & 0xFFu) << 24);
+        if (k0 == 168 && valid) x = (x & 0xFFFF0000u) | 0x0101u;
+        A[mq][s][m] = (int)x;
       }
-      __syncthreads();
-      if (wave_live) {
-#pragma unroll 1
-        for (int c = 0; c < kSub / 32; ++c) {
-          v4i B[6];
-          const uint8_t *src = lds + (32 * c + (lane & 31)) * kRecStride + 16 * (lane >> 5);
-#pragma unroll
-          for (int s = 0; s < 6; ++s) B[s] = *reinterpret_cast<const v4i *>(src + 32 * s);
-          v16i acc[kMQ];
-#pragma unroll
-          for (int mq = 0; mq < kMQ; ++mq) {
-            v16i zero = {};
-            acc[mq] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[mq][0], B[0], zero, 0, 0, 0);
-#pragma unroll
-            for (int s = 1; s < 6; ++s)
-              acc[mq] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[mq][s], B[s], acc[mq], 0, 0, 0);
-          }
-          int32_t any = 0;
-#pragma unroll
-          for (int mq = 0; mq < kMQ; ++mq)
-#pragma unroll
-            for (int e = 0; e < 16; ++e) any |= acc[mq][e];
-          if (__ballot(any < 0) == 0) continue;
-          // slow path: decode (query row, record) of every negative entry.
-          // Output layout of a 32x32 tile: lane holds column lane & 31 and rows
-          // 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3), e = 0..15.
-          const uint64_t g = sub + 32 * c + (lane & 31);
-#pragma unroll
-          for (int mq = 0; mq < kMQ; ++mq) {
-#pragma unroll
-            for (int e = 0; e < 16; ++e) {
-              const int32_t u = acc[mq][e];
-              const uint32_t row =
-                  wv * (kMQ * 32) + mq * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-              if (u < 0 && row < qb.count && g < g1) {
-                const uint32_t q = ws.perm[qb.first + row];
-                const uint32_t d = (uint32_t)(u + (int32_t)ws.T[q] + 1);
-                const QueryInfo *qi = ws.qinfo + q;
-                const uint32_t pos = atomicAdd(ws.count + q, 1u);
-                if (pos < qi->cap) ws.cand[qi->cand_off + pos] = ((uint64_t)d << 32) | g;
-              }
-            }
-          }
-        }
-      }
-      __syncthreads();
     }
   }
 }
 
-void launch_scan_mfma_i8(const Lib &lib, const Workspace &ws, uint32_t nqb, uint64_t items,
-                         int cus, hipStream_t s) {
+template <int MQ>
+__device__ __forceinline__ void load_b(const uint8_t *buf, int c, uint32_t lane, v4i (&B)[6]) {
+  const uint8_t *src = buf + (32 * c + (lane & 31)) * kRecStride + 16 * (lane >> 5);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) B[k] = *reinterpret_cast<const v4i *>(src + 32 * k);
+}
+
+template <int MQ>
+__device__ __forceinline__ void multiply(const v4i (&A)[MQ][6], const v4i (&B)[6],
+                                         v16i (&acc)[MQ]) {
+#pragma unroll
+  for (int mq = 0; mq < MQ; ++mq) {
+    v16i zero = {};
+    acc[mq] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[mq][0], B[0], zero, 0, 0, 0);
+#pragma unroll
+    for (int k = 1; k < 6; ++k)
+      acc[mq] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[mq][k], B[k], acc[mq], 0, 0, 0);
+  }
+}
+
+// Appends the hits of one 32x32 result tile (column block c of stage st).
+template <int MQ>
+__device__ __forceinline__ void decode(const Workspace &ws, const QBlock &qb, const Stage &st,
+                                       int c, uint32_t wv, uint32_t lane,
+                                       const v16i (&acc)[MQ]) {
+  // lane holds column lane & 31 and rows 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3)
+  const uint64_t g = st.g0 + 32 * c + (lane & 31);
+  const uint32_t half = lane >> 5;
+  const uint32_t below = (uint32_t)((1ull << (lane & 31)) - 1ull);
+#pragma unroll
+  for (int mq = 0; mq < MQ; ++mq) {
+#pragma unroll 1
+    for (int e = 0; e < 16; ++e) {
+      const int32_t u = acc[mq][e];
+      const uint32_t row = wv * (MQ * 32) + mq * 32 + 8 * (e >> 2) + 4 * half + (e & 3);
+      const bool hit = u < 0 && row < qb.count && g < st.g1;
+      const uint64_t bal = __ballot(hit);
+      if (bal == 0) continue;
+      const uint32_t mine = (uint32_t)(bal >> (32 * half));
+      uint32_t base = 0;
+      uint32_t q = 0;
+      if (mine) q = ws.perm[qb.first + row];
+      if (mine && (lane & 31) == (uint32_t)(__ffs(mine) - 1))
+        base = atomicAdd(ws.count + q, (uint32_t)__popc(mine));
+      // leader of each half: its lowest hit lane
+      const uint32_t lead = mine ? 32 * half + (uint32_t)(__ffs(mine) - 1) : lane;
+      base = __shfl(base, (int)lead);
+      if (hit) {
+        const QueryInfo *qi = ws.qinfo + q;
+        const uint32_t pos = base + (uint32_t)__popc(mine & below);
+        const uint32_t d = (uint32_t)(u + (int32_t)ws.T[q] + 1);
+        if (pos < qi->cap) ws.cand[qi->cand_off + pos] = ((uint64_t)d << 32) | g;
+      }
+    }
+  }
+}
+
+template <int MQ, int WPE>
+__global__ __launch_bounds__(256, WPE) void k_scan_mfma_i8(Lib lib, Workspace ws, uint32_t nqb,
+                                                           const uint64_t *item_off,
+                                                           uint64_t tile_lo, uint64_t items,
+                                                           uint64_t per_block) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[2][kSub * kRecStride];
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const uint64_t it0 = (uint64_t)blockIdx.x * per_block;
+  const uint64_t it1 = min(it0 + per_block, items);
+  if (it0 >= it1) return;
+  const uint64_t nst = (it1 - it0) * kSubPerTile;
+  v4i A[MQ][6];
+  uint32_t a_qb = 0xFFFFFFFFu;
+  QBlock qb{};
+  bool wave_live = false;
+
+  // item descriptions are computed half an item ahead of the stage prefetch
+  Item pinfo = describe(ws, item_off, nqb, tile_lo, it0);
+  Item ninfo = pinfo;
+  Stage cur = stage_of(pinfo, 0);
+  Stage nxt = stage_of(pinfo, 1);
+  const Regs R0 = load_stage(lib, cur, tid);
+  Regs R1 = load_stage(lib, nxt, tid);
+  expand(R0, lds[0], tid);
+  __syncthreads();
+  for (uint64_t s = 0; s < nst; ++s) {
+    // prefetch stage s + 2
+    Stage nn = nxt;
+    Regs R2 = R1;
+    const uint64_t s2 = s + 2;
+    if (s2 < nst) {
+      const uint32_t sub = (uint32_t)(s2 % kSubPerTile);
+      if (sub == 0) pinfo = ninfo;
+      nn = stage_of(pinfo, sub);
+      R2 = load_stage(lib, nn, tid);
+      if (sub == kSubPerTile / 2 && it0 + s2 / kSubPerTile + 1 < it1)
+        ninfo = describe(ws, item_off, nqb, tile_lo, it0 + s2 / kSubPerTile + 1);
+    }
+    // multiply stage s
+    if (cur.b != a_qb) {
+      a_qb = cur.b;
+      qb = ws.qblocks[cur.b];
+      wave_live = qb.count > wv * (MQ * 32);
+      build_a<MQ>(ws, qb, wv, lane, A);
+    }
+    if (wave_live && cur.g1 > cur.g0) {
+      const uint8_t *buf = lds[s & 1];
+      int32_t any = 0;
+      v4i B0[6], B1[6];
+      load_b<MQ>(buf, 0, lane, B0);
+#pragma unroll
+      for (int c = 0; c < kSub / 32; c += 2) {
+        v16i acc[MQ];
+        load_b<MQ>(buf, c + 1, lane, B1);
+        multiply<MQ>(A, B0, acc);
+#pragma unroll
+        for (int mq = 0; mq < MQ; ++mq)
+#pragma unroll
+          for (int e = 0; e < 16; ++e) any |= acc[mq][e];
+        if (c + 2 < kSub / 32) load_b<MQ>(buf, c + 2, lane, B0);
+        multiply<MQ>(A, B1, acc);
+#pragma unroll
+        for (int mq = 0; mq < MQ; ++mq)
+#pragma unroll
+          for (int e = 0; e < 16; ++e) any |= acc[mq][e];
+      }
+      if (__ballot(any < 0) != 0) {
+        // rare: multiply again column by column and append the hits
+#pragma unroll 1
+        for (int c = 0; c < kSub / 32; ++c) {
+          v16i acc[MQ];
+          load_b<MQ>(buf, c, lane, B0);
+          multiply<MQ>(A, B0, acc);
+          int32_t a2 = 0;
+#pragma unroll
+          for (int mq = 0; mq < MQ; ++mq)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) a2 |= acc[mq][e];
+          if (__ballot(a2 < 0) != 0) decode<MQ>(ws, qb, cur, c, wv, lane, acc);
+        }
+      }
+    }
+    // expand stage s + 1 into the other buffer
+    if (s + 1 < nst) expand(R1, lds[(s + 1) & 1], tid);
+    __syncthreads();
+    cur = nxt;
+    nxt = nn;
+    R1 = R2;
+  }
+}
+
+// Tile-shape variants (queries per wave = 32 * MQ, waves-per-SIMD hint).
+int mfma_variants() { return 4; }
+
+uint32_t mfma_qblock(int variant) {
+  switch (variant) {
+    case 2: return 4 * 4 * 32;
+    case 3: return 4 * 1 * 32;
+    default: return 4 * 2 * 32;
+  }
+}
+
+void launch_scan_mfma_i8(const Lib &lib, const Workspace &ws, uint32_t nqb,
+                         const uint64_t *item_off, uint64_t tile_lo, uint64_t items, int cus,
+                         int variant, hipStream_t s) {
   if (items == 0) return;
-  uint64_t blocks = (uint64_t)cus * 2;
+  const int per_cu = variant == 1 || variant == 3 ? 2 : 1;
+  uint64_t blocks = (uint64_t)cus * per_cu;
   if (blocks > items) blocks = items;
   const uint64_t per = (items + blocks - 1) / blocks;
   blocks = (items + per - 1) / per;
-  hipLaunchKernelGGL(k_scan_mfma_i8, dim3((uint32_t)blocks), dim3(256), 0, s, lib, ws, nqb,
-                     items, per);
+  const dim3 g((uint32_t)blocks), b(256);
+  switch (variant) {
+    case 1: hipLaunchKernelGGL((k_scan_mfma_i8<2, 2>), g, b, 0, s, lib, ws, nqb, item_off, tile_lo, items, per); break;
+    case 2: hipLaunchKernelGGL((k_scan_mfma_i8<4, 1>), g, b, 0, s, lib, ws, nqb, item_off, tile_lo, items, per); break;
+    case 3: hipLaunchKernelGGL((k_scan_mfma_i8<1, 2>), g, b, 0, s, lib, ws, nqb, item_off, tile_lo, items, per); break;
+    default: hipLaunchKernelGGL((k_scan_mfma_i8<2, 1>), g, b, 0, s, lib, ws, nqb, item_off, tile_lo, items, per); break;
+  }
 }
 
 }  // namespace fps

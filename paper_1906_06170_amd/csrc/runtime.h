@@ -5,7 +5,6 @@
 
 #include "fps_internal.h"
 
-constexpr uint64_t kDefaultSample = 1ull << 20;
 
 // Host state of one search in flight: pinned staging, timing events, counters.
 // The handle owns one; every server slot owns its own, so slots can run
@@ -25,12 +24,14 @@ struct fps_library {
   uint64_t n = 0, np = 0;
   uint32_t nstrides = 0;
   uint64_t strides[FPS_MAX_STRIDES + 1] = {};
-  uint64_t *dev = nullptr;  // caller-owned rows: w0 = dev, w1 = dev + np, w2 = dev + 2 np
+  uint64_t *dev = nullptr;  // caller-owned library arrays a, b, c, d (fps_internal.h)
   int device = 0;
   int cus = 256;
   fps_path path = FPS_PATH_AUTO;
+  int variant = -1;  // matrix-core tile shape, -1 = tuner's choice
   double cand_scale = 1.0;
-  uint64_t sample = kDefaultSample;
+  uint64_t sample = fps::kDefaultBoundSample;  // records of the bound sample
+  uint64_t phase_a = fps::kDefaultPhaseA;      // first phase boundary (0 = from the schedule)
   int force_fb = 0;
   SearchCtx ctx;  // staging of direct calls on this handle
 };
@@ -41,10 +42,11 @@ struct Plan {
   std::vector<fps::RangeSet> rsets;
   std::vector<fps::QueryInfo> qinfo;
   std::vector<uint32_t> perm;
+  std::vector<uint64_t> bounds;  // scan phase boundaries in records (last = UINT64_MAX)
   uint64_t total_cand = 0, total_out = 0, max_sample = 0;
   size_t off_rsets = 0, off_qinfo = 0, off_perm = 0, off_qblocks = 0, off_qbitem = 0,
          off_bblocks = 0, params_bytes = 0;
-  size_t off_T = 0, off_count = 0, off_flags = 0, off_hist = 0, off_cand = 0, off_out = 0,
+  size_t off_bdone = 0, off_T = 0, off_count = 0, off_flags = 0, off_hist = 0, off_cand = 0, off_out = 0,
          off_fbh = 0, off_fbo = 0, off_fbt = 0, total_bytes = 0;
 };
 

@@ -68,7 +68,29 @@ static fps_status ensure_pinned(void **p, size_t *have, size_t need) {
 // ---------------------------------------------------------------------------
 extern "C" size_t fps_library_device_bytes(uint64_t n) {
   const uint64_t np = (n + kRowAlign - 1) / kRowAlign * kRowAlign;
-  return (size_t)(np * 3 * sizeof(uint64_t));
+  return (size_t)(np * kBytesPerRecord);
+}
+
+// Library-layout words of a fingerprint given as three words with key j at bit
+// (j & 63) of word (j >> 6): key 160 moves into the always-zero bit 0 of a, keys
+// 161..166 go to d (see fps_internal.h).
+static inline void relabel(const uint64_t *w, uint64_t *a, uint64_t *b, uint32_t *c,
+                           uint32_t *d) {
+  *a = w[0] | ((w[2] >> 32) & 1ull);
+  *b = w[1];
+  *c = (uint32_t)w[2];
+  *d = (uint32_t)((w[2] >> 33) & 0x3Full);
+}
+
+static Lib lib_view(const fps_library *lib) {
+  Lib L;
+  L.a = lib->dev;
+  L.b = lib->dev + lib->np;
+  L.c = (const uint32_t *)(lib->dev + 2 * lib->np);
+  L.d = (const uint8_t *)((const uint32_t *)(lib->dev + 2 * lib->np) + lib->np);
+  L.n = lib->n;
+  L.np = lib->np;
+  return L;
 }
 
 SearchCtx::~SearchCtx() {
@@ -129,12 +151,16 @@ extern "C" fps_status fps_library_load(const uint64_t *host_words, uint64_t n,
       break;
     }
     if ((rc = L->ctx.init())) break;
-    // transpose record-major host words to word-major device rows, in chunks
+    // relabel and transpose record-major host words into the four device arrays
     const uint64_t CH = 1u << 20;
     void *pin = nullptr;
     size_t pin_bytes = 0;
-    if ((rc = ensure_pinned(&pin, &pin_bytes, 3 * CH * sizeof(uint64_t)))) break;
-    uint64_t *stage = (uint64_t *)pin;
+    if ((rc = ensure_pinned(&pin, &pin_bytes, CH * kBytesPerRecord))) break;
+    uint64_t *sa = (uint64_t *)pin, *sb = sa + CH;
+    uint32_t *sc = (uint32_t *)(sb + CH);
+    uint8_t *sd = (uint8_t *)(sc + CH);
+    uint8_t *da = (uint8_t *)L->dev, *db = da + 8 * L->np, *dc = db + 8 * L->np,
+            *dd = dc + 4 * L->np;
     for (uint64_t c0 = 0; c0 < n && !rc; c0 += CH) {
       const uint64_t c1 = std::min(n, c0 + CH), m = c1 - c0;
       if (hipStreamSynchronize(s) != hipSuccess) {
@@ -142,20 +168,24 @@ extern "C" fps_status fps_library_load(const uint64_t *host_words, uint64_t n,
         break;
       }
       for (uint64_t i = 0; i < m; ++i) {
-        stage[i] = host_words[3 * (c0 + i)];
-        stage[CH + i] = host_words[3 * (c0 + i) + 1];
-        stage[2 * CH + i] = host_words[3 * (c0 + i) + 2];
+        uint32_t c, d;
+        relabel(host_words + 3 * (c0 + i), &sa[i], &sb[i], &c, &d);
+        sc[i] = c;
+        sd[i] = (uint8_t)d;
       }
-      for (int w = 0; w < 3; ++w)
-        if (hipMemcpyAsync(L->dev + w * L->np + c0, stage + w * CH, m * sizeof(uint64_t),
-                           hipMemcpyHostToDevice, s) != hipSuccess)
-          rc = fps_fail(FPS_E_DEVICE, "upload failed");
+      if (hipMemcpyAsync(da + 8 * c0, sa, 8 * m, hipMemcpyHostToDevice, s) != hipSuccess ||
+          hipMemcpyAsync(db + 8 * c0, sb, 8 * m, hipMemcpyHostToDevice, s) != hipSuccess ||
+          hipMemcpyAsync(dc + 4 * c0, sc, 4 * m, hipMemcpyHostToDevice, s) != hipSuccess ||
+          hipMemcpyAsync(dd + c0, sd, m, hipMemcpyHostToDevice, s) != hipSuccess)
+        rc = fps_fail(FPS_E_DEVICE, "upload failed");
     }
-    if (!rc && L->np > n)
-      for (int w = 0; w < 3; ++w)
-        if (hipMemsetAsync(L->dev + w * L->np + n, 0, (L->np - n) * sizeof(uint64_t), s) !=
-            hipSuccess)
-          rc = fps_fail(FPS_E_DEVICE, "hipMemsetAsync failed");
+    const uint64_t tail = L->np - n;
+    if (!rc && tail &&
+        (hipMemsetAsync(da + 8 * n, 0, 8 * tail, s) != hipSuccess ||
+         hipMemsetAsync(db + 8 * n, 0, 8 * tail, s) != hipSuccess ||
+         hipMemsetAsync(dc + 4 * n, 0, 4 * tail, s) != hipSuccess ||
+         hipMemsetAsync(dd + n, 0, tail, s) != hipSuccess))
+      rc = fps_fail(FPS_E_DEVICE, "hipMemsetAsync failed");
     if (!rc && hipStreamSynchronize(s) != hipSuccess)
       rc = fps_fail(FPS_E_DEVICE, "stream synchronize failed");
     (void)hipHostFree(pin);
@@ -193,14 +223,25 @@ extern "C" fps_status fps_set_path(fps_library *lib, fps_path path) {
   return FPS_OK;
 }
 
+extern "C" fps_status fps_set_variant(fps_library *lib, int variant) {
+  fps_clear_error();
+  if (!lib) return fps_fail(FPS_E_ARG, "NULL library");
+  if (variant < -1 || variant >= mfma_variants())
+    return fps_fail(FPS_E_ARG, "variant %d out of range", variant);
+  lib->variant = variant;
+  return FPS_OK;
+}
+
 extern "C" fps_status fps_set_tuning(fps_library *lib, double candidate_scale,
-                                     uint64_t sample_records, int force_fallback) {
+                                     uint64_t sample_records, uint64_t phase_records,
+                                     int force_fallback) {
   fps_clear_error();
   if (!lib) return fps_fail(FPS_E_ARG, "NULL library");
   if (!(candidate_scale > 0.0) || !std::isfinite(candidate_scale))
     return fps_fail(FPS_E_ARG, "candidate_scale must be positive");
   lib->cand_scale = candidate_scale;
-  lib->sample = sample_records ? sample_records : kDefaultSample;
+  lib->sample = sample_records ? sample_records : kDefaultBoundSample;
+  lib->phase_a = phase_records ? phase_records : kDefaultPhaseA;
   lib->force_fb = force_fallback;
   return FPS_OK;
 }
@@ -255,9 +296,37 @@ fps_status fps_make_rangeset(const fps_library *lib, uint32_t mask, RangeSet *rs
   return FPS_OK;
 }
 
-static uint32_t capacity(const fps_library *lib, uint64_t keff, uint64_t neff, uint64_t sample) {
+// Scan phases.  The first bound comes from a sample of S1 records; the scan then
+// proceeds in phases whose boundaries grow geometrically (b1 = G * S1, b2 =
+// G * b1, ...), and after each phase the bound is refined to the keff-th
+// smallest distance of the prefix scanned so far.  A phase [b_i, b_i+1) then
+// appends about keff * (b_i+1 - b_i) / b_i records, times a small factor for
+// ties at the bound; G = 4096 / keff (clamped to 8..64) keeps that near a few
+// thousand per query.
+static std::vector<uint64_t> phase_bounds(const fps_library *lib, uint64_t max_neff,
+                                          uint64_t max_keff) {
+  std::vector<uint64_t> b{0};
+  const uint64_t G = std::min<uint64_t>(64, std::max<uint64_t>(8, 4096 / std::max<uint64_t>(max_keff, 1)));
+  uint64_t a = lib->phase_a ? lib->phase_a : std::max<uint64_t>(lib->sample, 1) * G;
+  while (a < max_neff && b.size() < (size_t)kMaxPhases) {
+    b.push_back(a);
+    a = a > (UINT64_MAX / G) ? UINT64_MAX : a * G;
+  }
+  b.push_back(UINT64_MAX);
+  return b;
+}
+
+// Candidate slots of a query: the expected appends of every phase (see
+// phase_bounds), times 8 for distance ties, plus slack; at most neff.
+static uint32_t capacity(const fps_library *lib, const std::vector<uint64_t> &bounds,
+                         uint64_t keff, uint64_t neff, uint64_t sample) {
   if (keff == 0 || neff == 0) return 0;
-  const double expected = sample ? (double)keff * (double)neff / (double)sample : (double)neff;
+  double expected = 0;
+  for (size_t i = 0; i + 1 < bounds.size() && bounds[i] < neff; ++i) {
+    const double lo = (double)bounds[i], hi = (double)std::min<uint64_t>(bounds[i + 1], neff);
+    const double ref = i == 0 ? (double)std::max<uint64_t>(sample, 1) : lo;
+    expected += (double)keff * (hi - lo) / ref;
+  }
   double cap = lib->cand_scale * (8.0 * expected + 4096.0);
   cap = std::min(cap, (double)neff);
   cap = std::max(cap, 1.0);
@@ -275,6 +344,7 @@ fps_status fps_plan(const fps_library *lib, uint32_t q, const uint32_t *k, const
   P->total_cand = 0;
   P->total_out = 0;
   P->max_sample = 0;
+  std::vector<uint32_t> rs_of(q);
   for (uint32_t i = 0; i < q; ++i) {
     const uint32_t m = mask ? mask[i] : FPS_MASK_ALL;
     auto it = seen.find(m);
@@ -289,12 +359,23 @@ fps_status fps_plan(const fps_library *lib, uint32_t q, const uint32_t *k, const
     } else {
       id = it->second;
     }
-    const RangeSet &rs = P->rsets[id];
+    rs_of[i] = id;
+  }
+  uint64_t max_neff = 0, max_keff = 0;
+  for (uint32_t i = 0; i < q; ++i) {
+    const uint64_t neff = P->rsets[rs_of[i]].neff;
+    const uint64_t keff = std::min<uint64_t>(k[i], neff);
+    if (keff) max_neff = std::max(max_neff, neff);
+    max_keff = std::max(max_keff, keff);
+  }
+  P->bounds = phase_bounds(lib, max_neff, max_keff);
+  for (uint32_t i = 0; i < q; ++i) {
+    const RangeSet &rs = P->rsets[rs_of[i]];
     QueryInfo &qi = P->qinfo[i];
-    qi.rset = id;
+    qi.rset = rs_of[i];
     qi.keff = (uint32_t)std::min<uint64_t>(k[i], rs.neff);
     qi.sample = std::min<uint64_t>(lib->sample, rs.neff);
-    qi.cap = capacity(lib, qi.keff, rs.neff, qi.sample);
+    qi.cap = capacity(lib, P->bounds, qi.keff, rs.neff, qi.sample);
     qi.cand_off = P->total_cand;
     qi.out_off = P->total_out;
     P->total_cand += qi.cap;
@@ -313,14 +394,16 @@ fps_status fps_plan(const fps_library *lib, uint32_t q, const uint32_t *k, const
   P->off_qinfo = take((size_t)q * sizeof(QueryInfo));
   P->off_perm = take((size_t)q * sizeof(uint32_t));
   P->off_qblocks = take(maxqb * sizeof(QBlock));
-  P->off_qbitem = take((maxqb + 1) * sizeof(uint64_t));
+  P->off_qbitem = take((size_t)kMaxPhases * (maxqb + 1) * sizeof(uint64_t));
   P->off_bblocks = take(maxqb * sizeof(QBlock));
   P->params_bytes = off;
+  P->off_bdone = take(maxqb * 4);
   P->off_T = take((size_t)q * 4);
+  P->off_hist = take((size_t)q * kHistCopies * kBins * 4);
+  P->off_cand = take(P->total_cand * sizeof(uint64_t));
+  // count, flags and the hits are contiguous: one copy brings them back
   P->off_count = take((size_t)q * 4);
   P->off_flags = take((size_t)q * 4);
-  P->off_hist = take((size_t)q * kBins * 4);
-  P->off_cand = take(P->total_cand * sizeof(uint64_t));
   P->off_out = take(P->total_out * sizeof(fps_hit));
   P->off_fbh = take((size_t)kFbWaves * kBins * 4);
   P->off_fbo = take((size_t)kFbWaves * kBins * 4);
@@ -341,34 +424,41 @@ extern "C" fps_status fps_workspace_bytes(const fps_library *lib, uint32_t q, co
 }
 
 // Groups queries by RangeSet into blocks of at most `qbs` queries; fills perm,
-// the blocks and the per-block work-item prefix (tiles of the block's range).
-void fps_make_blocks(Plan *P, uint32_t qbs, std::vector<QBlock> *blocks,
-                     std::vector<uint64_t> *item_off, bool items_single_tiles) {
+// the blocks, and for every scan phase the prefix of work items (batch tiles of
+// the phase) over the blocks: items[p * (nblocks + 1) + b].
+void fps_make_blocks(Plan *P, uint32_t qbs, const std::vector<uint64_t> &tile_bounds,
+                     std::vector<QBlock> *blocks, std::vector<uint64_t> *items) {
   P->perm.clear();
   blocks->clear();
-  item_off->clear();
-  uint64_t items = 0;
   for (uint32_t r = 0; r < P->rsets.size(); ++r) {
     const uint32_t first = (uint32_t)P->perm.size();
     for (uint32_t i = 0; i < P->q; ++i)
       if (P->qinfo[i].rset == r && P->qinfo[i].keff > 0) P->perm.push_back(i);
     const uint32_t cnt = (uint32_t)P->perm.size() - first;
     const RangeSet &rs = P->rsets[r];
-    const uint64_t tiles = items_single_tiles ? rs.t1off[rs.nranges] : rs.tboff[rs.nranges];
     for (uint32_t f = 0; f < cnt; f += qbs) {
       QBlock b{};
       b.first = first + f;
       b.count = std::min(qbs, cnt - f);
       b.rset = r;
+      b.tiles = (uint32_t)rs.tboff[rs.nranges];
       blocks->push_back(b);
-      item_off->push_back(items);
-      items += tiles;
     }
   }
-  item_off->push_back(items);
   // queries with keff = 0 go last (never scanned)
   for (uint32_t i = 0; i < P->q; ++i)
     if (P->qinfo[i].keff == 0) P->perm.push_back(i);
+  const size_t nb = blocks->size(), np = tile_bounds.size() - 1;
+  items->assign(np * (nb + 1), 0);
+  for (size_t p = 0; p < np; ++p) {
+    uint64_t acc = 0;
+    for (size_t b = 0; b < nb; ++b) {
+      (*items)[p * (nb + 1) + b] = acc;
+      const uint64_t t = (*blocks)[b].tiles;
+      acc += std::min(tile_bounds[p + 1], t) - std::min(tile_bounds[p], t);
+    }
+    (*items)[p * (nb + 1) + nb] = acc;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -380,8 +470,9 @@ static Workspace ws_view(const Plan &P, uint8_t *base) {
   w.qinfo = (QueryInfo *)(base + P.off_qinfo);
   w.perm = (uint32_t *)(base + P.off_perm);
   w.qblocks = (QBlock *)(base + P.off_qblocks);
-  w.qb_item_off = (uint64_t *)(base + P.off_qbitem);
+  w.qb_item = (uint64_t *)(base + P.off_qbitem);
   w.bblocks = (QBlock *)(base + P.off_bblocks);
+  w.bdone = (uint32_t *)(base + P.off_bdone);
   w.T = (uint32_t *)(base + P.off_T);
   w.count = (uint32_t *)(base + P.off_count);
   w.flags = (uint32_t *)(base + P.off_flags);
@@ -400,13 +491,23 @@ static fps_path resolve_path(fps_library *lib, const Plan &P, fps_path requested
 static fps_status launch_search(fps_library *lib, SearchCtx *ctx, Plan &P, fps_path path,
                                 uint8_t *wsbase, hipStream_t s) {
   const Workspace ws = ws_view(P, wsbase);
-  Lib L{lib->dev, lib->dev + lib->np, lib->dev + 2 * lib->np, lib->n, lib->np};
+  const Lib L = lib_view(lib);
+  // scan phases in tiles of the single-query kernel and of the batched kernels
+  const size_t nphases = P.bounds.size() - 1;
+  std::vector<uint64_t> t1b(nphases + 1), tbb(nphases + 1);
+  for (size_t i = 0; i <= nphases; ++i) {
+    const uint64_t b = P.bounds[i];
+    t1b[i] = b == UINT64_MAX ? UINT64_MAX : (b + kScanTile - 1) / kScanTile;
+    tbb[i] = b == UINT64_MAX ? UINT64_MAX : (b + kBatchTile - 1) / kBatchTile;
+  }
   // blocks for the bound kernel and for the batched scan
   std::vector<QBlock> bblocks, qblocks;
   std::vector<uint64_t> bitems, qitems;
-  fps_make_blocks(&P, kBoundQBlock, &bblocks, &bitems, false);
-  uint32_t qbs = path == FPS_PATH_MFMA_I8 ? (uint32_t)kMfmaQBlock : (uint32_t)kPopQBlock;
-  fps_make_blocks(&P, qbs, &qblocks, &qitems, false);
+  fps_make_blocks(&P, kBoundQBlock, tbb, &bblocks, &bitems);
+  const int variant = lib->variant >= 0 ? lib->variant % mfma_variants() : 0;
+  const uint32_t qbs = path == FPS_PATH_MFMA_I8 ? mfma_qblock(variant) : (uint32_t)kPopQBlock;
+  fps_make_blocks(&P, qbs, tbb, &qblocks, &qitems);
+  const uint32_t nqb = (uint32_t)qblocks.size();
   // parameter upload
   fps_status rc = ensure_pinned(&ctx->h_params, &ctx->h_params_bytes, P.params_bytes);
   if (rc) return rc;
@@ -419,21 +520,28 @@ static fps_status launch_search(fps_library *lib, SearchCtx *ctx, Plan &P, fps_p
   std::memcpy(h + P.off_bblocks, bblocks.data(), bblocks.size() * sizeof(QBlock));
   HIP_TRY(hipMemcpyAsync(wsbase, h, P.params_bytes, hipMemcpyHostToDevice, s));
   HIP_TRY(hipEventRecord(ctx->ev[0], s));
-  launch_prep(ws, P.q, s);
+  launch_prep(ws, P.q, (uint32_t)bblocks.size(), s);
   launch_bound(L, ws, (uint32_t)bblocks.size(), P.max_sample, s);
-  launch_threshold(ws, P.q, s);
   HIP_TRY(hipEventRecord(ctx->ev[1], s));
-  if (path == FPS_PATH_SINGLE) {
-    for (uint32_t i = 0; i < P.q; ++i) {
-      const QueryInfo &qi = P.qinfo[i];
-      if (qi.keff == 0) continue;
-      const RangeSet &rs = P.rsets[qi.rset];
-      launch_scan_single(L, ws, i, rs.t1off[rs.nranges], lib->cus, s);
+  for (size_t p = 0; p < nphases; ++p) {
+    if (p > 0) launch_refine(ws, P.q, s);
+    if (path == FPS_PATH_SINGLE) {
+      for (uint32_t i = 0; i < P.q; ++i) {
+        const QueryInfo &qi = P.qinfo[i];
+        if (qi.keff == 0) continue;
+        const RangeSet &rs = P.rsets[qi.rset];
+        const uint64_t tiles = rs.t1off[rs.nranges];
+        launch_scan_single(L, ws, i, std::min(t1b[p], tiles), std::min(t1b[p + 1], tiles),
+                           lib->cus, s);
+      }
+    } else {
+      const uint64_t *item_off = ws.qb_item + p * (nqb + 1);
+      const uint64_t items = qitems[p * (nqb + 1) + nqb];
+      if (path == FPS_PATH_POPCOUNT)
+        launch_scan_popcount(L, ws, nqb, item_off, tbb[p], items, lib->cus, s);
+      else
+        launch_scan_mfma_i8(L, ws, nqb, item_off, tbb[p], items, lib->cus, variant, s);
     }
-  } else if (path == FPS_PATH_POPCOUNT) {
-    launch_scan_popcount(L, ws, (uint32_t)qblocks.size(), qitems.back(), lib->cus, s);
-  } else {
-    launch_scan_mfma_i8(L, ws, (uint32_t)qblocks.size(), qitems.back(), lib->cus, s);
   }
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(ctx->ev[2], s));
@@ -464,10 +572,10 @@ fps_status fps_search_impl(fps_library *lib, SearchCtx *ctx, const uint64_t *que
   if (((uintptr_t)workspace & 255) != 0)
     return fps_fail(FPS_E_ARG, "workspace must be 256-byte aligned");
   for (uint32_t i = 0; i < q; ++i) {
-    std::memcpy(P.qinfo[i].w, queries + 3 * (size_t)i, 3 * sizeof(uint64_t));
-    P.qinfo[i].popc = (uint32_t)(__builtin_popcountll(P.qinfo[i].w[0]) +
-                                 __builtin_popcountll(P.qinfo[i].w[1]) +
-                                 __builtin_popcountll(P.qinfo[i].w[2]));
+    QueryInfo &qi = P.qinfo[i];
+    relabel(queries + 3 * (size_t)i, &qi.qa, &qi.qb, &qi.qc, &qi.qd);
+    qi.popc = (uint32_t)(__builtin_popcountll(qi.qa) + __builtin_popcountll(qi.qb) +
+                         __builtin_popcount(qi.qc) + __builtin_popcount(qi.qd));
   }
   out_offset[0] = 0;
   for (uint32_t i = 0; i < q; ++i) out_offset[i + 1] = out_offset[i] + P.qinfo[i].keff;
@@ -479,24 +587,22 @@ fps_status fps_search_impl(fps_library *lib, SearchCtx *ctx, const uint64_t *que
   uint8_t *wsb = (uint8_t *)workspace;
   rc = launch_search(lib, ctx, P, path, wsb, s);
   if (rc) return rc;
-  // results and per-query status back to the host
+  // per-query counts and flags and the hits come back in one copy
   const size_t out_bytes = P.total_out * sizeof(fps_hit);
-  const size_t stat_bytes = (size_t)q * 8;
-  rc = ensure_pinned(&ctx->h_out, &ctx->h_out_bytes, out_bytes + stat_bytes + 256);
+  const size_t back_bytes = P.off_out + out_bytes - P.off_count;
+  rc = ensure_pinned(&ctx->h_out, &ctx->h_out_bytes, back_bytes);
   if (rc) return rc;
   uint8_t *ho = (uint8_t *)ctx->h_out;
-  uint32_t *h_count = (uint32_t *)(ho);
-  uint32_t *h_flags = (uint32_t *)(ho + (size_t)q * 4);
-  fps_hit *h_hits = (fps_hit *)(ho + align_up(stat_bytes, 256));
-  HIP_TRY(hipMemcpyAsync(h_count, wsb + P.off_count, (size_t)q * 4, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(h_flags, wsb + P.off_flags, (size_t)q * 4, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(h_hits, wsb + P.off_out, out_bytes, hipMemcpyDeviceToHost, s));
+  uint32_t *h_count = (uint32_t *)ho;
+  uint32_t *h_flags = (uint32_t *)(ho + (P.off_flags - P.off_count));
+  fps_hit *h_hits = (fps_hit *)(ho + (P.off_out - P.off_count));
+  HIP_TRY(hipMemcpyAsync(ho, wsb + P.off_count, back_bytes, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   float ms = 0;
   if (hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]) == hipSuccess) ctx->last.scan_ms = ms;
   if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[3]) == hipSuccess) ctx->last.total_ms = ms;
   const Workspace ws = ws_view(P, wsb);
-  Lib L{lib->dev, lib->dev + lib->np, lib->dev + 2 * lib->np, lib->n, lib->np};
+  const Lib L = lib_view(lib);
   for (uint32_t i = 0; i < q; ++i) {
     ctx->last.candidates += h_count[i];
     const QueryInfo &qi = P.qinfo[i];

@@ -36,10 +36,10 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_device_bytes_layout(lib):
-    assert lib.fps_library_device_bytes(1) == 4096 * 24
-    assert lib.fps_library_device_bytes(4096) == 4096 * 24
-    assert lib.fps_library_device_bytes(4097) == 8192 * 24
-    assert lib.fps_library_device_bytes(95_417_114) == 95_420_416 * 24
+    assert lib.fps_library_device_bytes(1) == 4096 * 21
+    assert lib.fps_library_device_bytes(4096) == 4096 * 21
+    assert lib.fps_library_device_bytes(4097) == 8192 * 21
+    assert lib.fps_library_device_bytes(95_417_114) == 95_420_416 * 21
 
 
 def test_host_side_errors(lib):
@@ -73,7 +73,7 @@ def test_host_side_errors(lib):
                                 None) == fps.FPS_E_ARG
     sz = ctypes.c_size_t()
     assert lib.fps_workspace_bytes(None, 1, None, None, ctypes.byref(sz)) == fps.FPS_E_ARG
-    assert lib.fps_set_tuning(None, 1.0, 0, 0) == fps.FPS_E_ARG
+    assert lib.fps_set_tuning(None, 1.0, 0, 0, 0) == fps.FPS_E_ARG
     assert lib.fps_set_path(None, 0) == fps.FPS_E_ARG
     assert lib.fps_library_free(None) == fps.FPS_OK
     assert lib.fps_server_destroy(None) == fps.FPS_OK

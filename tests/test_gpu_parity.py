@@ -85,6 +85,24 @@ def test_batch_paths_uneven_k_masks(small, path):
     check_batch(lib_np, lib, qs, k, masks, path, "uneven k and masks")
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_mfma_variants(small, variant):
+    """Every matrix-core tile shape gives the oracle's answer (partial query
+    blocks included: 600 queries over 3 masks)."""
+    lib_np, lib = small
+    nq = 600
+    qs = fpsynth.batch_queries(lib_np, nq, 40 + variant).words
+    k, masks = fpsynth.uneven_params(nq, 41)
+    lib.set_variant(variant)
+    try:
+        check_batch(lib_np, lib, qs, k, masks, fps.PATH_MFMA_I8, f"variant {variant}")
+        lib.set_tuning(sample_records=2048, phase_records=10_000)
+        check_batch(lib_np, lib, qs, k, masks, fps.PATH_MFMA_I8, f"variant {variant} 2-phase")
+    finally:
+        lib.set_tuning()
+        lib.set_variant(-1)
+
+
 @pytest.mark.parametrize("path", PATHS)
 def test_all_masks_and_strides(small, path):
     lib_np, lib = small
@@ -131,11 +149,29 @@ def test_forced_fallback(small, path):
         lib.set_tuning()
 
 
+@pytest.mark.parametrize("sample,phase", [(1024, 2048), (1024, 20_000), (5000, 33_333),
+                                          (64, 512), (100_000, 4096)])
+@pytest.mark.parametrize("path", PATHS)
+def test_two_phase_bounds(small, path, sample, phase):
+    """Small bound samples and short first phases: the refined bound path."""
+    lib_np, lib = small
+    nq = 150
+    qs = fpsynth.batch_queries(lib_np, nq, 31).words
+    k, masks = fpsynth.uneven_params(nq, 32)
+    lib.set_tuning(sample_records=sample, phase_records=phase)
+    try:
+        check_batch(lib_np, lib, qs, k, masks, path, f"sample {sample} phase {phase}")
+        got = lib.search(qs[0], 30)
+        assert np.array_equal(got, oracle.search(lib_np.words, qs[0], 30))
+    finally:
+        lib.set_tuning()
+
+
 @pytest.mark.parametrize("path", PATHS)
 def test_overflow_fallback(small, path):
     lib_np, lib = small
     qs = fpsynth.batch_queries(lib_np, 70, 8).words
-    lib.set_tuning(candidate_scale=1e-6, sample_records=1024)
+    lib.set_tuning(candidate_scale=1e-6, sample_records=1024, phase_records=4096)
     try:
         st = check_batch(lib_np, lib, qs, 30, None, path, "overflow")
         assert st["fallbacks"] > 0
