@@ -69,7 +69,11 @@ typedef struct {
 
 /* Scan kernels a batch may use. */
 typedef enum {
-  FPS_PATH_AUTO = 0,     /* autotuner's choice (timed on first use per batch shape) */
+  FPS_PATH_AUTO = 0,     /* autotuner's choice: on the first batch of a shape (live
+                            queries, largest k, library size, each rounded up to a
+                            power of two) every applicable kernel is timed and the
+                            fastest is kept; FPS_TUNE_CACHE names a file that
+                            persists the choices as JSON lines */
   FPS_PATH_SINGLE = 1,   /* the single-query scan, one query per pass over the library */
   FPS_PATH_POPCOUNT = 2, /* batched XOR + popcount kernel */
   FPS_PATH_MFMA_I8 = 3,  /* batched int8 matrix-core kernel (a.b with exact int32 sums) */
@@ -118,7 +122,8 @@ fps_status fps_set_path(fps_library *lib, fps_path path);
 
 /* Selects the tile shape of the matrix-core kernel: 0 = 64 queries per wave,
  * 1 = 64 per wave with two waves per SIMD, 2 = 128 per wave, 3 = 32 per wave
- * with two waves per SIMD; -1 (default) lets the autotuner choose.  Results
+ * with two waves per SIMD, 4 = 64 queries shared by a block's four waves,
+ * which split the records; -1 (default) lets the autotuner choose.  Results
  * never depend on it.  Errors: FPS_E_ARG. */
 fps_status fps_set_variant(fps_library *lib, int variant);
 
@@ -176,7 +181,7 @@ typedef struct {
   uint32_t path;          /* fps_path actually used */
   uint32_t queries;       /* queries in the call */
   uint32_t fallbacks;     /* queries answered by the exact two-pass fallback */
-  uint32_t reserved;
+  uint32_t variant;       /* matrix-core tile shape used (fps_set_variant) */
   uint64_t candidates;    /* candidates appended by the scan, summed over queries */
   double scan_ms;         /* device time of the scan kernel(s) of the call */
   double total_ms;        /* device time from the first to the last kernel */

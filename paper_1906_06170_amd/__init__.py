@@ -40,7 +40,7 @@ class FPSError(RuntimeError):
 
 class SearchStats(ctypes.Structure):
     _fields_ = [("path", ctypes.c_uint32), ("queries", ctypes.c_uint32),
-                ("fallbacks", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("fallbacks", ctypes.c_uint32), ("variant", ctypes.c_uint32),
                 ("candidates", ctypes.c_uint64), ("scan_ms", ctypes.c_double),
                 ("total_ms", ctypes.c_double)]
 
@@ -233,7 +233,7 @@ class Library:
         st = SearchStats()
         _check(load_library().fps_last_search_stats(self._handle, ctypes.byref(st)))
         return {"path": PATH_NAMES.get(st.path, st.path), "queries": st.queries,
-                "fallbacks": st.fallbacks, "candidates": st.candidates,
+                "fallbacks": st.fallbacks, "candidates": st.candidates, "variant": st.variant,
                 "scan_ms": st.scan_ms, "total_ms": st.total_ms}
 
     # -- search ---------------------------------------------------------------

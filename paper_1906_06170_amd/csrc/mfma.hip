@@ -144,11 +144,11 @@ __device__ __forceinline__ void expand(const Regs &R, uint8_t *buf, uint32_t tid
 
 // A operands of wave wv: row i = lane & 31 of tile mq; K slice 16 * (lane >> 5).
 template <int MQ>
-__device__ __forceinline__ void build_a(const Workspace &ws, const QBlock &qb, uint32_t wv,
+__device__ __forceinline__ void build_a(const Workspace &ws, const QBlock &qb, uint32_t row0,
                                         uint32_t lane, v4i (&A)[MQ][6]) {
 #pragma unroll
   for (int mq = 0; mq < MQ; ++mq) {
-    const uint32_t row = wv * (MQ * 32) + mq * 32 + (lane & 31);
+    const uint32_t row = row0 + mq * 32 + (lane & 31);
     uint64_t qa = 0, qbw = 0;
     uint32_t qcw = 0, qdw = 0;
     int32_t qc = 254;
@@ -201,7 +201,7 @@ __device__ __forceinline__ void multiply(const v4i (&A)[MQ][6], const v4i (&B)[6
 // Appends the hits of one 32x32 result tile (column block c of stage st).
 template <int MQ>
 __device__ __forceinline__ void decode(const Workspace &ws, const QBlock &qb, const Stage &st,
-                                       int c, uint32_t wv, uint32_t lane,
+                                       int c, uint32_t row0, uint32_t lane,
                                        const v16i (&acc)[MQ]) {
   // lane holds column lane & 31 and rows 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3)
   const uint64_t g = st.g0 + 32 * c + (lane & 31);
@@ -212,7 +212,7 @@ __device__ __forceinline__ void decode(const Workspace &ws, const QBlock &qb, co
 #pragma unroll 1
     for (int e = 0; e < 16; ++e) {
       const int32_t u = acc[mq][e];
-      const uint32_t row = wv * (MQ * 32) + mq * 32 + 8 * (e >> 2) + 4 * half + (e & 3);
+      const uint32_t row = row0 + mq * 32 + 8 * (e >> 2) + 4 * half + (e & 3);
       const bool hit = u < 0 && row < qb.count && g < st.g1;
       const uint64_t bal = __ballot(hit);
       if (bal == 0) continue;
@@ -235,7 +235,11 @@ __device__ __forceinline__ void decode(const Workspace &ws, const QBlock &qb, co
   }
 }
 
-template <int MQ, int WPE>
+// COLS = false: the 4 waves hold different queries (128 * MQ per block) and
+// each multiplies every column of a stage.  COLS = true: the 4 waves hold the
+// same 32 * MQ queries and wave w multiplies column w of every stage (for
+// small batches, so that no wave idles).
+template <int MQ, int WPE, bool COLS>
 __global__ __launch_bounds__(256, WPE) void k_scan_mfma_i8(Lib lib, Workspace ws, uint32_t nqb,
                                                            const uint64_t *item_off,
                                                            uint64_t tile_lo, uint64_t items,
@@ -246,6 +250,7 @@ __global__ __launch_bounds__(256, WPE) void k_scan_mfma_i8(Lib lib, Workspace ws
   const uint64_t it1 = min(it0 + per_block, items);
   if (it0 >= it1) return;
   const uint64_t nst = (it1 - it0) * kSubPerTile;
+  const uint32_t row0 = COLS ? 0u : wv * (MQ * 32);
   v4i A[MQ][6];
   uint32_t a_qb = 0xFFFFFFFFu;
   QBlock qb{};
@@ -277,10 +282,23 @@ __global__ __launch_bounds__(256, WPE) void k_scan_mfma_i8(Lib lib, Workspace ws
     if (cur.b != a_qb) {
       a_qb = cur.b;
       qb = ws.qblocks[cur.b];
-      wave_live = qb.count > wv * (MQ * 32);
-      build_a<MQ>(ws, qb, wv, lane, A);
+      wave_live = qb.count > row0;
+      build_a<MQ>(ws, qb, row0, lane, A);
     }
-    if (wave_live && cur.g1 > cur.g0) {
+    if (COLS && wave_live && cur.g0 + 32 * wv < cur.g1) {
+      const uint8_t *buf = lds[s & 1];
+      v4i B0[6];
+      v16i acc[MQ];
+      load_b<MQ>(buf, (int)wv, lane, B0);
+      multiply<MQ>(A, B0, acc);
+      int32_t any = 0;
+#pragma unroll
+      for (int mq = 0; mq < MQ; ++mq)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) any |= acc[mq][e];
+      if (__ballot(any < 0) != 0) decode<MQ>(ws, qb, cur, (int)wv, row0, lane, acc);
+    }
+    if (!COLS && wave_live && cur.g1 > cur.g0) {
       const uint8_t *buf = lds[s & 1];
       int32_t any = 0;
       v4i B0[6], B1[6];
@@ -313,7 +331,7 @@ __global__ __launch_bounds__(256, WPE) void k_scan_mfma_i8(Lib lib, Workspace ws
           for (int mq = 0; mq < MQ; ++mq)
 #pragma unroll
             for (int e = 0; e < 16; ++e) a2 |= acc[mq][e];
-          if (__ballot(a2 < 0) != 0) decode<MQ>(ws, qb, cur, c, wv, lane, acc);
+          if (__ballot(a2 < 0) != 0) decode<MQ>(ws, qb, cur, c, row0, lane, acc);
         }
       }
     }
@@ -326,13 +344,19 @@ __global__ __launch_bounds__(256, WPE) void k_scan_mfma_i8(Lib lib, Workspace ws
   }
 }
 
-// Tile-shape variants (queries per wave = 32 * MQ, waves-per-SIMD hint).
-int mfma_variants() { return 4; }
+// Tile-shape variants.
+//   0: 64 queries per wave, 256 per block, one wave per SIMD
+//   1: 64 queries per wave, 256 per block, two waves per SIMD
+//   2: 128 queries per wave, 512 per block
+//   3: 32 queries per wave, 128 per block, two waves per SIMD
+//   4: 64 queries shared by the 4 waves, which split the columns (small batches)
+int mfma_variants() { return 5; }
 
 uint32_t mfma_qblock(int variant) {
   switch (variant) {
     case 2: return 4 * 4 * 32;
     case 3: return 4 * 1 * 32;
+    case 4: return 2 * 32;
     default: return 4 * 2 * 32;
   }
 }
@@ -341,18 +365,23 @@ void launch_scan_mfma_i8(const Lib &lib, const Workspace &ws, uint32_t nqb,
                          const uint64_t *item_off, uint64_t tile_lo, uint64_t items, int cus,
                          int variant, hipStream_t s) {
   if (items == 0) return;
-  const int per_cu = variant == 1 || variant == 3 ? 2 : 1;
+  const int per_cu = variant == 1 || variant == 3 || variant == 4 ? 2 : 1;
   uint64_t blocks = (uint64_t)cus * per_cu;
   if (blocks > items) blocks = items;
   const uint64_t per = (items + blocks - 1) / blocks;
   blocks = (items + per - 1) / per;
   const dim3 g((uint32_t)blocks), b(256);
+#define FPS_MFMA_LAUNCH(MQ, WPE, COLS)                                                     \
+  hipLaunchKernelGGL((k_scan_mfma_i8<MQ, WPE, COLS>), g, b, 0, s, lib, ws, nqb, item_off, \
+                     tile_lo, items, per)
   switch (variant) {
-    case 1: hipLaunchKernelGGL((k_scan_mfma_i8<2, 2>), g, b, 0, s, lib, ws, nqb, item_off, tile_lo, items, per); break;
-    case 2: hipLaunchKernelGGL((k_scan_mfma_i8<4, 1>), g, b, 0, s, lib, ws, nqb, item_off, tile_lo, items, per); break;
-    case 3: hipLaunchKernelGGL((k_scan_mfma_i8<1, 2>), g, b, 0, s, lib, ws, nqb, item_off, tile_lo, items, per); break;
-    default: hipLaunchKernelGGL((k_scan_mfma_i8<2, 1>), g, b, 0, s, lib, ws, nqb, item_off, tile_lo, items, per); break;
+    case 1: FPS_MFMA_LAUNCH(2, 2, false); break;
+    case 2: FPS_MFMA_LAUNCH(4, 1, false); break;
+    case 3: FPS_MFMA_LAUNCH(1, 2, false); break;
+    case 4: FPS_MFMA_LAUNCH(2, 2, true); break;
+    default: FPS_MFMA_LAUNCH(2, 1, false); break;
   }
+#undef FPS_MFMA_LAUNCH
 }
 
 }  // namespace fps

@@ -1,6 +1,9 @@
 // Host-side state of the C ABI shared by the runtime and the server.
 #pragma once
 #include <map>
+#include <mutex>
+#include <tuple>
+#include <utility>
 #include <vector>
 
 #include "fps_internal.h"
@@ -20,6 +23,12 @@ struct SearchCtx {
   ~SearchCtx();
 };
 
+// Batch shape for the autotuner: log2 of live queries, largest k, library size.
+struct TuneKey {
+  uint32_t q, k, n;
+  bool operator<(const TuneKey &o) const { return std::tie(q, k, n) < std::tie(o.q, o.k, o.n); }
+};
+
 struct fps_library {
   uint64_t n = 0, np = 0;
   uint32_t nstrides = 0;
@@ -34,6 +43,8 @@ struct fps_library {
   uint64_t phase_a = fps::kDefaultPhaseA;      // first phase boundary (0 = from the schedule)
   int force_fb = 0;
   SearchCtx ctx;  // staging of direct calls on this handle
+  std::mutex tune_mu;
+  std::map<TuneKey, std::pair<fps_path, int>> tuned;
 };
 
 // A planned search: per-query parameters and the byte layout of the workspace.

@@ -6,7 +6,9 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <map>
 #include <string>
 #include <vector>
@@ -42,6 +44,8 @@ extern "C" const char *fps_last_error(void) { return t_err.c_str(); }
   } while (0)
 
 static inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+static void tune_load(fps_library *lib);
 
 static bool bad_fingerprint(const uint64_t *w) {
   return (w[0] & 1ull) != 0 || (w[2] >> 39) != 0;
@@ -151,6 +155,7 @@ extern "C" fps_status fps_library_load(const uint64_t *host_words, uint64_t n,
       break;
     }
     if ((rc = L->ctx.init())) break;
+    tune_load(L);
     // relabel and transpose record-major host words into the four device arrays
     const uint64_t CH = 1u << 20;
     void *pin = nullptr;
@@ -485,11 +490,14 @@ static Workspace ws_view(const Plan &P, uint8_t *base) {
   return w;
 }
 
-static fps_path resolve_path(fps_library *lib, const Plan &P, fps_path requested, bool single);
+static fps_status launch_search(fps_library *lib, SearchCtx *ctx, Plan &P, fps_path path,
+                                int variant, uint8_t *wsbase, hipStream_t s);
+static fps_status resolve_path(fps_library *lib, SearchCtx *ctx, Plan &P, fps_path requested,
+                               uint8_t *wsb, hipStream_t s, fps_path *path, int *variant);
 
 // Launches the whole search of a planned batch on stream s (no host sync).
 static fps_status launch_search(fps_library *lib, SearchCtx *ctx, Plan &P, fps_path path,
-                                uint8_t *wsbase, hipStream_t s) {
+                                int variant, uint8_t *wsbase, hipStream_t s) {
   const Workspace ws = ws_view(P, wsbase);
   const Lib L = lib_view(lib);
   // scan phases in tiles of the single-query kernel and of the batched kernels
@@ -504,7 +512,6 @@ static fps_status launch_search(fps_library *lib, SearchCtx *ctx, Plan &P, fps_p
   std::vector<QBlock> bblocks, qblocks;
   std::vector<uint64_t> bitems, qitems;
   fps_make_blocks(&P, kBoundQBlock, tbb, &bblocks, &bitems);
-  const int variant = lib->variant >= 0 ? lib->variant % mfma_variants() : 0;
   const uint32_t qbs = path == FPS_PATH_MFMA_I8 ? mfma_qblock(variant) : (uint32_t)kPopQBlock;
   fps_make_blocks(&P, qbs, tbb, &qblocks, &qitems);
   const uint32_t nqb = (uint32_t)qblocks.size();
@@ -582,10 +589,14 @@ fps_status fps_search_impl(fps_library *lib, SearchCtx *ctx, const uint64_t *que
   ctx->last = fps_search_stats{};
   ctx->last.queries = q;
   if (P.total_out == 0) return FPS_OK;
-  const fps_path path = resolve_path(lib, P, forced, false);
-  ctx->last.path = (uint32_t)path;
   uint8_t *wsb = (uint8_t *)workspace;
-  rc = launch_search(lib, ctx, P, path, wsb, s);
+  fps_path path;
+  int variant;
+  rc = resolve_path(lib, ctx, P, forced, wsb, s, &path, &variant);
+  if (rc) return rc;
+  ctx->last.path = (uint32_t)path;
+  ctx->last.variant = path == FPS_PATH_MFMA_I8 ? (uint32_t)variant : 0u;
+  rc = launch_search(lib, ctx, P, path, variant, wsb, s);
   if (rc) return rc;
   // per-query counts and flags and the hits come back in one copy
   const size_t out_bytes = P.total_out * sizeof(fps_hit);
@@ -645,14 +656,112 @@ extern "C" fps_status fps_search_batch(fps_library *lib, const uint64_t *queries
 }
 
 // ---------------------------------------------------------------------------
-// path choice
+// autotuner: the batch scan kernel (path and matrix-core tile shape) for a
+// batch shape is chosen by timing every applicable candidate on the first
+// batch of that shape (device time between the first and the last kernel);
+// the winner is cached per (live queries, largest k, library size), each
+// rounded up to a power of two, and optionally persisted as JSON lines in the
+// file named by FPS_TUNE_CACHE.  Every candidate returns identical results.
 // ---------------------------------------------------------------------------
-static fps_path resolve_path(fps_library *lib, const Plan &P, fps_path requested, bool) {
-  if (requested != FPS_PATH_AUTO) return requested;
-  if (lib->path != FPS_PATH_AUTO) return lib->path == FPS_PATH_MFMA_F4 ? FPS_PATH_MFMA_I8 : lib->path;
-  uint32_t live = 0;
+static uint32_t pow2_ceil(uint64_t x) {
+  uint32_t p = 0;
+  while (p < 63 && (1ull << p) < x) ++p;
+  return p;
+}
+
+static TuneKey tune_key(const Plan &P) {
+  uint64_t live = 0, kmax = 0, nmax = 0;
+  for (const auto &qi : P.qinfo)
+    if (qi.keff) {
+      ++live;
+      kmax = std::max<uint64_t>(kmax, qi.keff);
+      nmax = std::max<uint64_t>(nmax, P.rsets[qi.rset].neff);
+    }
+  return TuneKey{pow2_ceil(live), pow2_ceil(kmax), pow2_ceil(nmax)};
+}
+
+static void tune_load(fps_library *lib) {
+  const char *path = std::getenv("FPS_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return;
+  char line[512];
+  while (std::fgets(line, sizeof line, f)) {
+    int cus = 0, q = 0, k = 0, n = 0, p = 0, v = 0;
+    if (std::sscanf(line, "{\"cus\": %d, \"q_log2\": %d, \"k_log2\": %d, \"n_log2\": %d, \"path\": %d, "
+                    "\"variant\": %d",
+                    &cus, &q, &k, &n, &p, &v) == 6 &&
+        cus == lib->cus && p >= FPS_PATH_SINGLE && p <= FPS_PATH_MFMA_I8)
+      lib->tuned[TuneKey{(uint32_t)q, (uint32_t)k, (uint32_t)n}] = {(fps_path)p, v};
+  }
+  std::fclose(f);
+}
+
+static void tune_save(const fps_library *lib, const TuneKey &key, fps_path p, int v, double ms) {
+  const char *path = std::getenv("FPS_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE *f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f,
+               "{\"cus\": %d, \"q_log2\": %u, \"k_log2\": %u, \"n_log2\": %u, \"path\": %d, "
+               "\"variant\": %d, \"ms\": %.4f}\n",
+               lib->cus, key.q, key.k, key.n, (int)p, v, ms);
+  std::fclose(f);
+}
+
+static std::vector<std::pair<fps_path, int>> tune_candidates(const Plan &P) {
+  uint64_t live = 0;
   for (const auto &qi : P.qinfo) live += qi.keff > 0;
-  if (live >= 64) return FPS_PATH_MFMA_I8;
-  if (live >= 4) return FPS_PATH_POPCOUNT;
-  return FPS_PATH_SINGLE;
+  std::vector<std::pair<fps_path, int>> c;
+  if (live <= 16) c.push_back({FPS_PATH_SINGLE, 0});
+  c.push_back({FPS_PATH_POPCOUNT, 0});
+  if (live >= 8)
+    for (int v = 0; v < mfma_variants(); ++v) c.push_back({FPS_PATH_MFMA_I8, v});
+  return c;
+}
+
+static fps_status resolve_path(fps_library *lib, SearchCtx *ctx, Plan &P, fps_path requested,
+                               uint8_t *wsb, hipStream_t s, fps_path *path, int *variant) {
+  *variant = lib->variant >= 0 ? lib->variant : 1;
+  if (requested != FPS_PATH_AUTO) {
+    *path = requested;
+    return FPS_OK;
+  }
+  if (lib->path != FPS_PATH_AUTO) {
+    *path = lib->path == FPS_PATH_MFMA_F4 ? FPS_PATH_MFMA_I8 : lib->path;
+    return FPS_OK;
+  }
+  const TuneKey key = tune_key(P);
+  {
+    std::lock_guard<std::mutex> lk(lib->tune_mu);
+    auto it = lib->tuned.find(key);
+    if (it != lib->tuned.end()) {
+      *path = it->second.first;
+      if (lib->variant < 0) *variant = it->second.second;
+      return FPS_OK;
+    }
+  }
+  double best = 1e30;
+  fps_path bp = FPS_PATH_POPCOUNT;
+  int bv = 0;
+  for (const auto &cand : tune_candidates(P)) {
+    fps_status rc = launch_search(lib, ctx, P, cand.first, cand.second, wsb, s);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(s));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[3]));
+    if (ms < best) {
+      best = ms;
+      bp = cand.first;
+      bv = cand.second;
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(lib->tune_mu);
+    lib->tuned[key] = {bp, bv};
+  }
+  tune_save(lib, key, bp, bv, best);
+  *path = bp;
+  if (lib->variant < 0) *variant = bv;
+  return FPS_OK;
 }

@@ -85,7 +85,7 @@ def test_batch_paths_uneven_k_masks(small, path):
     check_batch(lib_np, lib, qs, k, masks, path, "uneven k and masks")
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 def test_mfma_variants(small, variant):
     """Every matrix-core tile shape gives the oracle's answer (partial query
     blocks included: 600 queries over 3 masks)."""
@@ -101,6 +101,28 @@ def test_mfma_variants(small, variant):
     finally:
         lib.set_tuning()
         lib.set_variant(-1)
+
+
+def test_autotuner_and_cache(tmp_path, monkeypatch):
+    """AUTO times every candidate on the first batch of a shape, caches the
+    winner (also in the FPS_TUNE_CACHE file), and a new handle reuses it."""
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("FPS_TUNE_CACHE", str(cache))
+    lib_np = fpsynth.make_library(50_000, 3)
+    lib = fps.Library(lib_np.words)
+    qs = fpsynth.batch_queries(lib_np, 100, 7).words
+    hits, off = lib.search_batch(qs, 30)
+    ohits, ooff = oracle.search_batch(lib_np.words, qs, 30)
+    assert np.array_equal(off, ooff) and np.array_equal(hits, ohits)
+    st = lib.last_stats()
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and '"path"' in lines[0]
+    lib2 = fps.Library(lib_np.words)
+    hits2, off2 = lib2.search_batch(qs, 30)
+    assert np.array_equal(hits2, hits)
+    assert len(cache.read_text().splitlines()) == 1  # cached: no second tuning
+    st2 = lib2.last_stats()
+    assert (st2["path"], st2["variant"]) == (st["path"], st["variant"])
 
 
 @pytest.mark.parametrize("path", PATHS)
