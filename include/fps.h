@@ -120,6 +120,14 @@ fps_status fps_library_free(fps_library *lib);
 /* Selects the batch scan kernel (default FPS_PATH_AUTO). */
 fps_status fps_set_path(fps_library *lib, fps_path path);
 
+/* Graph replay of batched searches (default on): when a launch shape (query
+ * count, per-query k and mask, workspace, kernel choice) comes again within the
+ * last 8 calls, its launch sequence is recorded into a HIP graph, and later
+ * calls of that shape replay it with the new queries (up to 4 graphs per
+ * handle or server slot).  Single-query scans always launch directly.
+ * enable = 0 launches every kernel directly. */
+fps_status fps_set_graphs(fps_library *lib, int enable);
+
 /* Selects the tile shape of the matrix-core kernel: 0 = 64 queries per wave,
  * 1 = 64 per wave with two waves per SIMD, 2 = 128 per wave, 3 = 32 per wave
  * with two waves per SIMD, 4 = 64 queries shared by a block's four waves,
@@ -183,8 +191,15 @@ typedef struct {
   uint32_t fallbacks;     /* queries answered by the exact two-pass fallback */
   uint32_t variant;       /* matrix-core tile shape used (fps_set_variant) */
   uint64_t candidates;    /* candidates appended by the scan, summed over queries */
-  double scan_ms;         /* device time of the scan kernel(s) of the call */
+  double scan_ms;         /* device time of the scan kernel launches of the call (HIP events) */
   double total_ms;        /* device time from the first to the last kernel */
+  uint32_t graph;         /* 1 if the launch sequence was replayed from a HIP graph */
+  uint32_t scan_launches; /* scan kernel launches of the call */
+  /* running sums over every call on this handle (or server slot) */
+  double scan_ms_sum;
+  double total_ms_sum;
+  uint64_t calls;
+  uint64_t scan_launches_sum;
 } fps_search_stats;
 
 fps_status fps_last_search_stats(const fps_library *lib, fps_search_stats *stats);

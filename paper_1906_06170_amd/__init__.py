@@ -42,7 +42,10 @@ class SearchStats(ctypes.Structure):
     _fields_ = [("path", ctypes.c_uint32), ("queries", ctypes.c_uint32),
                 ("fallbacks", ctypes.c_uint32), ("variant", ctypes.c_uint32),
                 ("candidates", ctypes.c_uint64), ("scan_ms", ctypes.c_double),
-                ("total_ms", ctypes.c_double)]
+                ("total_ms", ctypes.c_double), ("graph", ctypes.c_uint32),
+                ("scan_launches", ctypes.c_uint32), ("scan_ms_sum", ctypes.c_double),
+                ("total_ms_sum", ctypes.c_double), ("calls", ctypes.c_uint64),
+                ("scan_launches_sum", ctypes.c_uint64)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -75,6 +78,7 @@ EXPORTS = {
     "fps_library_free": (ctypes.c_int, [ctypes.c_void_p]),
     "fps_set_path": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "fps_set_variant": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "fps_set_graphs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "fps_workspace_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_void_p]),
     "fps_search": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
@@ -217,6 +221,10 @@ class Library:
     def set_path(self, path: int):
         _check(load_library().fps_set_path(self._handle, int(path)))
 
+    def set_graphs(self, enable: bool):
+        """Replay repeated launch shapes from HIP graphs (default on)."""
+        _check(load_library().fps_set_graphs(self._handle, int(bool(enable))))
+
     def set_variant(self, variant: int):
         """Matrix-core tile shape (0..3, or -1 for the tuner's choice)."""
         _check(load_library().fps_set_variant(self._handle, int(variant)))
@@ -234,7 +242,10 @@ class Library:
         _check(load_library().fps_last_search_stats(self._handle, ctypes.byref(st)))
         return {"path": PATH_NAMES.get(st.path, st.path), "queries": st.queries,
                 "fallbacks": st.fallbacks, "candidates": st.candidates, "variant": st.variant,
-                "scan_ms": st.scan_ms, "total_ms": st.total_ms}
+                "scan_ms": st.scan_ms, "total_ms": st.total_ms, "graph": bool(st.graph),
+                "scan_launches": st.scan_launches, "scan_ms_sum": st.scan_ms_sum,
+                "total_ms_sum": st.total_ms_sum, "calls": st.calls,
+                "scan_launches_sum": st.scan_launches_sum}
 
     # -- search ---------------------------------------------------------------
     def search(self, query, k: int, mask: int = MASK_ALL, stream=None) -> np.ndarray:

@@ -118,6 +118,12 @@ void launch_scan_mfma_i8(const Lib &lib, const Workspace &ws, uint32_t nqb,
                          int variant, hipStream_t s);
 int mfma_variants();
 uint32_t mfma_qblock(int variant);
+// ---- launchers (mfma_f4.hip) ----
+void launch_scan_mfma_f4(const Lib &lib, const Workspace &ws, uint32_t nqb,
+                         const uint64_t *item_off, uint64_t tile_lo, uint64_t items, int cus,
+                         int variant, hipStream_t s);
+int mfma_f4_variants();
+uint32_t mfma_f4_qblock(int variant);
 
 constexpr int kPopQBlock = 128;   // queries per block of the popcount kernel
 constexpr int kBoundQBlock = 32;  // queries per block of the bound kernel

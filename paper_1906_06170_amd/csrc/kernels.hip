@@ -220,8 +220,11 @@ void launch_refine(const Workspace &ws, uint32_t q, hipStream_t s) {
 // 512-record tile per iteration in four groups of 128 records; in each group a
 // lane takes two consecutive records, so every load instruction of the wave
 // reads one contiguous segment (16-byte loads of a and b, 8-byte of c, 2-byte
-// of d): 16 loads, 168 bytes per lane in flight.
+// of d): 16 loads, 168 bytes per lane in flight.  The library is streamed once
+// per query, so the loads are nontemporal (they bypass cache retention).
 // ---------------------------------------------------------------------------
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+
 __global__ __launch_bounds__(256) void k_scan_single(Lib lib, Workspace ws, uint32_t qidx,
                                                      uint64_t t_begin, uint64_t t_end) {
   const QueryInfo *qi = ws.qinfo + qidx;
@@ -240,22 +243,24 @@ __global__ __launch_bounds__(256) void k_scan_single(Lib lib, Workspace ws, uint
     while (t >= rs->t1off[r + 1]) ++r;
     const uint64_t rb = rs->begin[r], re = rs->end[r];
     const uint64_t base = (rb & ~(uint64_t)(kScanTile - 1)) + (t - rs->t1off[r]) * kScanTile;
-    ulonglong2 A[4], B[4];
-    uint2 C[4];
+    u64x2 A[4], B[4];
+    uint64_t C[4];
     uint32_t D[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const uint64_t i = base + 128 * u + 2 * lane;
-      A[u] = *reinterpret_cast<const ulonglong2 *>(lib.a + i);
-      B[u] = *reinterpret_cast<const ulonglong2 *>(lib.b + i);
-      C[u] = *reinterpret_cast<const uint2 *>(lib.c + i);
-      D[u] = *reinterpret_cast<const uint16_t *>(lib.d + i);
+      A[u] = __builtin_nontemporal_load(reinterpret_cast<const u64x2 *>(lib.a + i));
+      B[u] = __builtin_nontemporal_load(reinterpret_cast<const u64x2 *>(lib.b + i));
+      C[u] = __builtin_nontemporal_load(reinterpret_cast<const uint64_t *>(lib.c + i));
+      D[u] = __builtin_nontemporal_load(reinterpret_cast<const uint16_t *>(lib.d + i));
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const uint64_t i = base + 128 * u + 2 * lane;
-      const int32_t d0 = (int32_t)dist4(A[u].x, B[u].x, C[u].x, D[u] & 0xFFu, qa, qb, qc, qd);
-      const int32_t d1 = (int32_t)dist4(A[u].y, B[u].y, C[u].y, D[u] >> 8, qa, qb, qc, qd);
+      const int32_t d0 =
+          (int32_t)dist4(A[u].x, B[u].x, (uint32_t)C[u], D[u] & 0xFFu, qa, qb, qc, qd);
+      const int32_t d1 =
+          (int32_t)dist4(A[u].y, B[u].y, (uint32_t)(C[u] >> 32), D[u] >> 8, qa, qb, qc, qd);
       const bool h0 = d0 <= T && i >= rb && i < re;
       const bool h1 = d1 <= T && i + 1 >= rb && i + 1 < re;
       wave_append(h0, ((uint64_t)d0 << 32) | i, cnt, cand, cap);
@@ -268,7 +273,7 @@ void launch_scan_single(const Lib &lib, const Workspace &ws, uint32_t qidx, uint
                         uint64_t t_end, int cus, hipStream_t s) {
   if (t_end <= t_begin) return;
   uint64_t blocks = (t_end - t_begin + 3) / 4;  // 4 waves per block
-  const uint64_t maxb = (uint64_t)cus * 8;
+  const uint64_t maxb = (uint64_t)cus * 32;
   if (blocks > maxb) blocks = maxb;
   hipLaunchKernelGGL(k_scan_single, dim3((uint32_t)blocks), dim3(256), 0, s, lib, ws, qidx,
                      t_begin, t_end);

@@ -32,16 +32,14 @@
 // again, column by column, to decode its hits.  In a 32x32 result tile the 32
 // lanes of a half-wave share one query row per accumulator element, so hits
 // are appended with one atomic per half-wave.
-#include "fps_internal.h"
+#include "mfma_common.h"
 
 namespace fps {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int kSub = 128;                       // records per LDS stage
-constexpr int kSubPerTile = kBatchTile / kSub;  // stages per work item
-constexpr int kRecStride = 208;                 // bytes per expanded record (192 + 16 pad)
+constexpr int kRecStride = 208;  // bytes per expanded record (192 + 16 pad)
 
 // Four key bits -> four bytes of value 0 or 1 (shifted copies do not overlap).
 __device__ __forceinline__ uint32_t spread4(uint32_t nib) {
@@ -59,62 +57,6 @@ __device__ __forceinline__ uint32_t chunk32(uint64_t a, uint64_t b, uint32_t c, 
     case 4: return c;
     default: return d;
   }
-}
-
-// A work item: query block b and the records [t0, t1) of one batch tile.
-struct Item {
-  uint32_t b;
-  uint64_t t0, t1;
-};
-
-// A stage: query block b and the records [g0, g1) (at most kSub, maybe none).
-struct Stage {
-  uint32_t b;
-  uint64_t g0, g1;
-};
-
-__device__ __forceinline__ Item describe(const Workspace &ws, const uint64_t *item_off,
-                                         uint32_t nqb, uint64_t tile_lo, uint64_t item) {
-  uint32_t b = 0;
-  while (b + 1 < nqb && item >= item_off[b + 1]) ++b;
-  const QBlock qb = ws.qblocks[b];
-  const RangeSet *rs = ws.rsets + qb.rset;
-  const uint64_t tile = item - item_off[b] + min(tile_lo, (uint64_t)qb.tiles);
-  uint32_t r = 0;
-  while (tile >= rs->tboff[r + 1]) ++r;
-  Item it;
-  it.b = b;
-  it.t0 = rs->begin[r] + (tile - rs->tboff[r]) * kBatchTile;
-  it.t1 = min(it.t0 + (uint64_t)kBatchTile, rs->end[r]);
-  return it;
-}
-
-__device__ __forceinline__ Stage stage_of(const Item &it, uint32_t sub) {
-  Stage st;
-  st.b = it.b;
-  st.g0 = min(it.t0 + (uint64_t)sub * kSub, it.t1);
-  st.g1 = min(st.g0 + (uint64_t)kSub, it.t1);
-  return st;
-}
-
-// Records of a stage held in registers: thread tid loads record tid >> 1.
-struct Regs {
-  uint64_t a, b;
-  uint32_t c, d;
-  uint32_t ok, pad;
-};
-
-__device__ __forceinline__ Regs load_stage(const Lib &lib, const Stage &st, uint32_t tid) {
-  Regs R;
-  const uint64_t g = st.g0 + (tid >> 1);
-  R.ok = g < st.g1 ? 1u : 0u;
-  R.pad = 0;
-  const uint64_t gs = R.ok ? g : 0;
-  R.a = lib.a[gs];
-  R.b = lib.b[gs];
-  R.c = lib.c[gs];
-  R.d = (uint32_t)lib.d[gs];
-  return R;
 }
 
 // Thread (record tid >> 1, half tid & 1) writes the 96 slots 96h .. 96h + 95.

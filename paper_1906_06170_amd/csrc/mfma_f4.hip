@@ -1,0 +1,330 @@
+// Batched scan on the gfx950 matrix cores with 4-bit float operands.
+//
+// The same contraction as the int8 kernel (d = |q| + |r| - 2 q.r, the matrix
+// form of Section 4.3), on v_mfma_scale_f32_32x32x64_f8f6f4 with both operands
+// in fp4 (e2m1) and unit block scales: twice the K of the int8 instruction per
+// issue.  Every operand value is one of {0, 1, -2, 6, 0.5 .. 6} and every
+// partial sum is an integer below 2^9, so the fp32 accumulation is exact.
+//
+// Per (query, record) pair the product is u = d - T_q - 1 (a candidate iff
+// u < 0):
+//   key digits      : query -2 * q_s, record r_s      -> -2 q.r
+//   accumulator init: |q| - T_q - 1 per query row     (the MFMA's C input)
+//   |r| digits      : 7 spare digits; query 6,6,6,6,6,6,1, record the digits
+//                     v_0..v_5, w of |r| = 6 (v_0 + .. + v_5) + w (a per-|r|
+//                     table in LDS)
+// Invalid rows start at +300 and invalid records carry |r| digits worth 216,
+// so neither can pass.
+//
+// Bit -> digit expansion: a 32-bit chunk of keys becomes 32 digits (16 bytes)
+// with four byte permutations (v_perm_b32) of a 4-entry table: output dword j,
+// byte b holds the digits of key bits 8b + 2j (low nibble) and 8b + 2j + 1.
+// Queries and records use the same order, which is all a dot product needs.
+// The six chunks of a record (lo a, hi a, lo b, hi b, c, d) are the six 16-byte
+// K fragments of its three MFMA K-steps; the |r| digits sit in dword 3 of the
+// d fragment, which holds bits 6, 7, 14, 15, ... of d (always zero).
+#include "mfma_common.h"
+
+namespace fps {
+
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef int v4i_ __attribute__((ext_vector_type(4)));
+
+constexpr int kF4Stride = 112;  // bytes per expanded record (96 + 16 pad)
+constexpr uint32_t kDigitsRecord = 0x22200200u;  // 2-bit index -> two digits of 1.0
+constexpr uint32_t kDigitsQuery = 0xCCC00C00u;   // 2-bit index -> two digits of -2.0
+constexpr uint32_t kQueryPopDigits = 0x02777777u;  // 6.0 x 6, 1.0
+constexpr uint32_t kInvalidPopDigits = 0x00777777u;  // worth 6 * 36 = 216
+
+__device__ __forceinline__ void spread_f4(uint32_t c, uint32_t table, uint32_t *o) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    o[j] = __builtin_amdgcn_perm(table, table, (c >> (2 * j)) & 0x03030303u);
+}
+
+// |r| = 6 * (v_0 + ... + v_5) + w as fp4 digits (v_i in {0, .5, 1, 1.5, 2, 3,
+// 4, 6}, w in {0, 1, 2}); 2 v_i taken greedily from {12, 8, 6, 4, 3, 2, 1}
+// covers every 3 m + w <= 166 within six digits.
+__device__ uint32_t pop_digits(uint32_t p) {
+  if (p > (uint32_t)kKeys) return kInvalidPopDigits;
+  uint32_t m = p / 3, w = p % 3, pat = 0;
+  const uint32_t two_v[7] = {12, 8, 6, 4, 3, 2, 1};
+  const uint32_t code[7] = {0x7, 0x6, 0x5, 0x4, 0x3, 0x2, 0x1};
+  for (int i = 0; i < 6; ++i) {
+    for (int c = 0; c < 7; ++c) {
+      if (two_v[c] <= m) {
+        pat |= code[c] << (4 * i);
+        m -= two_v[c];
+        break;
+      }
+    }
+  }
+  pat |= (w == 0 ? 0u : (w == 1 ? 0x2u : 0x4u)) << 24;
+  return pat;
+}
+
+// Thread (record tid >> 1, half tid & 1) writes fragments 3h .. 3h + 2.
+__device__ __forceinline__ void expand_f4(const Regs &R, uint8_t *buf, const uint32_t *poptab,
+                                          uint32_t tid) {
+  const uint32_t rr = tid >> 1, h = tid & 1;
+  const uint64_t ra = R.ok ? R.a : 0, rb = R.ok ? R.b : 0;
+  const uint32_t rc = R.ok ? R.c : 0, rd = R.ok ? R.d : 0;
+  const uint32_t ch[3] = {h ? (uint32_t)(rb >> 32) : (uint32_t)ra, h ? rc : (uint32_t)(ra >> 32),
+                          h ? rd : (uint32_t)rb};
+  uint32_t dw[12];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) spread_f4(ch[f], kDigitsRecord, dw + 4 * f);
+  if (h == 1) {
+    const uint32_t pr = (uint32_t)(__popcll(ra) + __popcll(rb) + __popc(rc) + __popc(rd));
+    dw[11] = poptab[R.ok ? pr : 255u];
+  }
+  v4i_ *dst = reinterpret_cast<v4i_ *>(buf + rr * kF4Stride + 48 * h);
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    v4i_ v = {(int)dw[4 * f], (int)dw[4 * f + 1], (int)dw[4 * f + 2], (int)dw[4 * f + 3]};
+    dst[f] = v;
+  }
+}
+
+// A operands and accumulator init of a wave: lane holds query row
+// row0 + mq * 32 + (lane & 31) for the A fragments (K half lane >> 5), and for
+// the C input the rows of the 32x32 output layout.
+template <int MQ>
+__device__ __forceinline__ void build_a_f4(const Workspace &ws, const QBlock &qb, uint32_t row0,
+                                           uint32_t lane, v8i (&A)[MQ][3], v16f (&C)[MQ]) {
+  const uint32_t h = lane >> 5;
+#pragma unroll
+  for (int mq = 0; mq < MQ; ++mq) {
+    const uint32_t row = row0 + mq * 32 + (lane & 31);
+    uint64_t qa = 0, qbw = 0;
+    uint32_t qcw = 0, qdw = 0;
+    float qc = 300.0f;
+    const bool valid = row < qb.count;
+    if (valid) {
+      const uint32_t q = ws.perm[qb.first + row];
+      qa = ws.qinfo[q].qa;
+      qbw = ws.qinfo[q].qb;
+      qcw = ws.qinfo[q].qc;
+      qdw = ws.qinfo[q].qd;
+      qc = (float)((int32_t)ws.qinfo[q].popc - (int32_t)ws.T[q] - 1);
+    }
+    const uint32_t ch[3] = {h ? (uint32_t)(qa >> 32) : (uint32_t)qa,
+                            h ? (uint32_t)(qbw >> 32) : (uint32_t)qbw, h ? qdw : qcw};
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      uint32_t o[4];
+      spread_f4(ch[s], kDigitsQuery, o);
+      if (s == 2 && h == 1) o[3] = valid ? kQueryPopDigits : 0u;
+      v8i v = {(int)o[0], (int)o[1], (int)o[2], (int)o[3], 0, 0, 0, 0};
+      A[mq][s] = v;
+    }
+    // C input: element e of this lane is row 8 (e >> 2) + 4 h + (e & 3) of the tile
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+      C[mq][e] = __shfl(qc, (int)(8 * (e >> 2) + 4 * h + (e & 3)));
+  }
+}
+
+template <int MQ>
+__device__ __forceinline__ void load_b_f4(const uint8_t *buf, int c, uint32_t lane,
+                                          v8i (&B)[3]) {
+  const uint8_t *src = buf + (32 * c + (lane & 31)) * kF4Stride + 16 * (lane >> 5);
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const v4i_ x = *reinterpret_cast<const v4i_ *>(src + 32 * s);
+    v8i v = {x[0], x[1], x[2], x[3], 0, 0, 0, 0};
+    B[s] = v;
+  }
+}
+
+template <int MQ>
+__device__ __forceinline__ void multiply_f4(const v8i (&A)[MQ][3], const v8i (&B)[3],
+                                            const v16f (&C)[MQ], v16f (&acc)[MQ]) {
+#pragma unroll
+  for (int mq = 0; mq < MQ; ++mq) {
+    acc[mq] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[mq][0], B[0], C[mq], 4, 4, 0, 127,
+                                                              0, 127);
+    acc[mq] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[mq][1], B[1], acc[mq], 4, 4, 0,
+                                                              127, 0, 127);
+    acc[mq] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[mq][2], B[2], acc[mq], 4, 4, 0,
+                                                              127, 0, 127);
+  }
+}
+
+template <int MQ>
+__device__ __forceinline__ int32_t or_bits(const v16f (&acc)[MQ]) {
+  int32_t any = 0;
+#pragma unroll
+  for (int mq = 0; mq < MQ; ++mq)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const float x = acc[mq][e];
+      any |= __float_as_int(x);
+    }
+  return any;
+}
+
+// Appends the hits of one 32x32 result tile (column block c of stage st); the
+// 32 lanes of a half-wave share one query row per element: one atomic each.
+template <int MQ>
+__device__ __forceinline__ void decode_f4(const Workspace &ws, const QBlock &qb, const Stage &st,
+                                          int c, uint32_t row0, uint32_t lane,
+                                          const v16f (&acc)[MQ]) {
+  const uint64_t g = st.g0 + 32 * c + (lane & 31);
+  const uint32_t half = lane >> 5;
+  const uint32_t below = (uint32_t)((1ull << (lane & 31)) - 1ull);
+#pragma unroll
+  for (int mq = 0; mq < MQ; ++mq) {
+#pragma unroll 1
+    for (int e = 0; e < 16; ++e) {
+      const float u = acc[mq][e];
+      const uint32_t row = row0 + mq * 32 + 8 * (e >> 2) + 4 * half + (e & 3);
+      const bool hit = u < 0.0f && row < qb.count && g < st.g1;
+      const uint64_t bal = __ballot(hit);
+      if (bal == 0) continue;
+      const uint32_t mine = (uint32_t)(bal >> (32 * half));
+      uint32_t base = 0, q = 0;
+      if (mine) q = ws.perm[qb.first + row];
+      if (mine && (lane & 31) == (uint32_t)(__ffs(mine) - 1))
+        base = atomicAdd(ws.count + q, (uint32_t)__popc(mine));
+      const uint32_t lead = mine ? 32 * half + (uint32_t)(__ffs(mine) - 1) : lane;
+      base = __shfl(base, (int)lead);
+      if (hit) {
+        const QueryInfo *qi = ws.qinfo + q;
+        const uint32_t pos = base + (uint32_t)__popc(mine & below);
+        const uint32_t d = (uint32_t)((int32_t)u + (int32_t)ws.T[q] + 1);
+        if (pos < qi->cap) ws.cand[qi->cand_off + pos] = ((uint64_t)d << 32) | g;
+      }
+    }
+  }
+}
+
+// COLS = false: the 4 waves hold different queries (128 * MQ per block).
+// COLS = true: the 4 waves share 32 * MQ queries and wave w multiplies column w.
+template <int MQ, int WPE, bool COLS>
+__global__ __launch_bounds__(256, WPE) void k_scan_mfma_f4(Lib lib, Workspace ws, uint32_t nqb,
+                                                           const uint64_t *item_off,
+                                                           uint64_t tile_lo, uint64_t items,
+                                                           uint64_t per_block) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[2][kSub * kF4Stride];
+  __shared__ uint32_t poptab[256];
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const uint64_t it0 = (uint64_t)blockIdx.x * per_block;
+  const uint64_t it1 = min(it0 + per_block, items);
+  if (it0 >= it1) return;
+  poptab[tid] = pop_digits(tid);
+  const uint64_t nst = (it1 - it0) * kSubPerTile;
+  const uint32_t row0 = COLS ? 0u : wv * (MQ * 32);
+  v8i A[MQ][3];
+  v16f C[MQ];
+  uint32_t a_qb = 0xFFFFFFFFu;
+  QBlock qb{};
+  bool wave_live = false;
+
+  Item pinfo = describe(ws, item_off, nqb, tile_lo, it0);
+  Item ninfo = pinfo;
+  Stage cur = stage_of(pinfo, 0);
+  Stage nxt = stage_of(pinfo, 1);
+  const Regs R0 = load_stage(lib, cur, tid);
+  Regs R1 = load_stage(lib, nxt, tid);
+  __syncthreads();  // poptab
+  expand_f4(R0, lds[0], poptab, tid);
+  __syncthreads();
+  for (uint64_t s = 0; s < nst; ++s) {
+    Stage nn = nxt;
+    Regs R2 = R1;
+    const uint64_t s2 = s + 2;
+    if (s2 < nst) {
+      const uint32_t sub = (uint32_t)(s2 % kSubPerTile);
+      if (sub == 0) pinfo = ninfo;
+      nn = stage_of(pinfo, sub);
+      R2 = load_stage(lib, nn, tid);
+      if (sub == kSubPerTile / 2 && it0 + s2 / kSubPerTile + 1 < it1)
+        ninfo = describe(ws, item_off, nqb, tile_lo, it0 + s2 / kSubPerTile + 1);
+    }
+    if (cur.b != a_qb) {
+      a_qb = cur.b;
+      qb = ws.qblocks[cur.b];
+      wave_live = qb.count > row0;
+      build_a_f4<MQ>(ws, qb, row0, lane, A, C);
+    }
+    const uint8_t *buf = lds[s & 1];
+    if (COLS && wave_live && cur.g0 + 32 * wv < cur.g1) {
+      v8i B[3];
+      v16f acc[MQ];
+      load_b_f4<MQ>(buf, (int)wv, lane, B);
+      multiply_f4<MQ>(A, B, C, acc);
+      if (__ballot(or_bits<MQ>(acc) < 0) != 0) decode_f4<MQ>(ws, qb, cur, (int)wv, row0, lane, acc);
+    }
+    if (!COLS && wave_live && cur.g1 > cur.g0) {
+      int32_t any = 0;
+      v8i B0[3], B1[3];
+      load_b_f4<MQ>(buf, 0, lane, B0);
+#pragma unroll
+      for (int c = 0; c < kSub / 32; c += 2) {
+        v16f acc[MQ];
+        load_b_f4<MQ>(buf, c + 1, lane, B1);
+        multiply_f4<MQ>(A, B0, C, acc);
+        any |= or_bits<MQ>(acc);
+        if (c + 2 < kSub / 32) load_b_f4<MQ>(buf, c + 2, lane, B0);
+        multiply_f4<MQ>(A, B1, C, acc);
+        any |= or_bits<MQ>(acc);
+      }
+      if (__ballot(any < 0) != 0) {
+#pragma unroll 1
+        for (int c = 0; c < kSub / 32; ++c) {
+          v16f acc[MQ];
+          load_b_f4<MQ>(buf, c, lane, B0);
+          multiply_f4<MQ>(A, B0, C, acc);
+          if (__ballot(or_bits<MQ>(acc) < 0) != 0) decode_f4<MQ>(ws, qb, cur, c, row0, lane, acc);
+        }
+      }
+    }
+    if (s + 1 < nst) expand_f4(R1, lds[(s + 1) & 1], poptab, tid);
+    __syncthreads();
+    cur = nxt;
+    nxt = nn;
+    R1 = R2;
+  }
+}
+
+// Tile-shape variants of the fp4 kernel.
+//   0: 64 queries per wave, 256 per block, two waves per SIMD
+//   1: 128 queries per wave, 512 per block
+//   2: 64 queries shared by the 4 waves, which split the columns (small batches)
+//   3: 32 queries per wave, 128 per block, two waves per SIMD
+int mfma_f4_variants() { return 4; }
+
+uint32_t mfma_f4_qblock(int variant) {
+  switch (variant) {
+    case 1: return 4 * 4 * 32;
+    case 2: return 2 * 32;
+    case 3: return 4 * 1 * 32;
+    default: return 4 * 2 * 32;
+  }
+}
+
+void launch_scan_mfma_f4(const Lib &lib, const Workspace &ws, uint32_t nqb,
+                         const uint64_t *item_off, uint64_t tile_lo, uint64_t items, int cus,
+                         int variant, hipStream_t s) {
+  if (items == 0) return;
+  const int per_cu = variant == 1 ? 1 : 2;
+  uint64_t blocks = (uint64_t)cus * per_cu;
+  if (blocks > items) blocks = items;
+  const uint64_t per = (items + blocks - 1) / blocks;
+  blocks = (items + per - 1) / per;
+  const dim3 g((uint32_t)blocks), b(256);
+#define FPS_F4_LAUNCH(MQ, WPE, COLS)                                                       \
+  hipLaunchKernelGGL((k_scan_mfma_f4<MQ, WPE, COLS>), g, b, 0, s, lib, ws, nqb, item_off, \
+                     tile_lo, items, per)
+  switch (variant) {
+    case 1: FPS_F4_LAUNCH(4, 1, false); break;
+    case 2: FPS_F4_LAUNCH(2, 2, true); break;
+    case 3: FPS_F4_LAUNCH(1, 2, false); break;
+    default: FPS_F4_LAUNCH(2, 2, false); break;
+  }
+#undef FPS_F4_LAUNCH
+}
+
+}  // namespace fps

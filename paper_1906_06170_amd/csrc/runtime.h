@@ -17,8 +17,19 @@ struct SearchCtx {
   size_t h_params_bytes = 0;
   void *h_out = nullptr;
   size_t h_out_bytes = 0;
-  hipEvent_t ev[4] = {};
+  // ev[0]/ev[1]: first and last kernel of a call; ev[2 + 2p], ev[3 + 2p]:
+  // around the scan launches of phase p
+  hipEvent_t ev[2 + 2 * fps::kMaxPhases] = {};
   fps_search_stats last{};
+  uint32_t last_phases = 0;
+  double sum_scan_ms = 0, sum_total_ms = 0;  // running sums since creation
+  uint64_t sum_calls = 0, sum_launches = 0;
+  // graph replay of repeated launch shapes (see run_search)
+  static constexpr size_t kGraphs = 4, kSeen = 8;
+  hipStream_t cap = nullptr;
+  std::vector<std::pair<std::vector<uint64_t>, hipGraphExec_t>> graphs;
+  std::vector<std::vector<uint64_t>> seen;
+  uint32_t graph_failures = 0;
   fps_status init();
   ~SearchCtx();
 };
@@ -42,6 +53,7 @@ struct fps_library {
   uint64_t sample = fps::kDefaultBoundSample;  // records of the bound sample
   uint64_t phase_a = fps::kDefaultPhaseA;      // first phase boundary (0 = from the schedule)
   int force_fb = 0;
+  bool graphs = true;  // capture and replay repeated launch shapes
   SearchCtx ctx;  // staging of direct calls on this handle
   std::mutex tune_mu;
   std::map<TuneKey, std::pair<fps_path, int>> tuned;

@@ -98,6 +98,8 @@ static Lib lib_view(const fps_library *lib) {
 }
 
 SearchCtx::~SearchCtx() {
+  for (auto &g : graphs) (void)hipGraphExecDestroy(g.second);
+  if (cap) (void)hipStreamDestroy(cap);
   if (h_params) (void)hipHostFree(h_params);
   if (h_out) (void)hipHostFree(h_out);
   for (auto &e : ev)
@@ -107,6 +109,7 @@ SearchCtx::~SearchCtx() {
 fps_status SearchCtx::init() {
   for (auto &e : ev)
     if (!e) HIP_TRY(hipEventCreate(&e));
+  if (!cap) HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
   return FPS_OK;
 }
 
@@ -228,10 +231,17 @@ extern "C" fps_status fps_set_path(fps_library *lib, fps_path path) {
   return FPS_OK;
 }
 
+extern "C" fps_status fps_set_graphs(fps_library *lib, int enable) {
+  fps_clear_error();
+  if (!lib) return fps_fail(FPS_E_ARG, "NULL library");
+  lib->graphs = enable != 0;
+  return FPS_OK;
+}
+
 extern "C" fps_status fps_set_variant(fps_library *lib, int variant) {
   fps_clear_error();
   if (!lib) return fps_fail(FPS_E_ARG, "NULL library");
-  if (variant < -1 || variant >= mfma_variants())
+  if (variant < -1 || variant >= std::max(mfma_variants(), mfma_f4_variants()))
     return fps_fail(FPS_E_ARG, "variant %d out of range", variant);
   lib->variant = variant;
   return FPS_OK;
@@ -491,13 +501,45 @@ static Workspace ws_view(const Plan &P, uint8_t *base) {
 }
 
 static fps_status launch_search(fps_library *lib, SearchCtx *ctx, Plan &P, fps_path path,
-                                int variant, uint8_t *wsbase, hipStream_t s);
+                                int variant, uint8_t *wsbase, hipStream_t s,
+                                bool capturing = false, bool d2h = false, bool host_only = false);
 static fps_status resolve_path(fps_library *lib, SearchCtx *ctx, Plan &P, fps_path requested,
                                uint8_t *wsb, hipStream_t s, fps_path *path, int *variant);
 
-// Launches the whole search of a planned batch on stream s (no host sync).
+// Timing events.  Inside a stream capture an event-record node is added after
+// the current capture frontier and the capture continues from it, so replays of
+// the graph record the events like an eager launch does.
+static fps_status record(hipEvent_t e, hipStream_t s, bool capturing) {
+  if (!capturing) {
+    HIP_TRY(hipEventRecord(e, s));
+    return FPS_OK;
+  }
+  hipStreamCaptureStatus st;
+  unsigned long long id = 0;
+  hipGraph_t g = nullptr;
+  const hipGraphNode_t *deps = nullptr;
+  size_t ndeps = 0;
+  HIP_TRY(hipStreamGetCaptureInfo_v2(s, &st, &id, &g, &deps, &ndeps));
+  if (st != hipStreamCaptureStatusActive || !g)
+    return fps_fail(FPS_E_DEVICE, "stream is not capturing");
+  hipGraphNode_t node = nullptr;
+  HIP_TRY(hipGraphAddEventRecordNode(&node, g, deps, ndeps, e));
+  HIP_TRY(hipStreamUpdateCaptureDependencies(s, &node, 1, hipStreamSetCaptureDependencies));
+  return FPS_OK;
+}
+
+// Bytes brought back after a search: per-query counts and flags, then the hits.
+static size_t back_bytes(const Plan &P) {
+  return P.off_out + P.total_out * sizeof(fps_hit) - P.off_count;
+}
+
+// Enqueues the whole search of a planned batch on stream s (no host sync):
+// parameter upload, prep, bound, the scan phases with refines, select, and
+// with d2h the copy of counts, flags and hits into the pinned staging.  Also
+// used under stream capture (capturing = true) to record a graph.
 static fps_status launch_search(fps_library *lib, SearchCtx *ctx, Plan &P, fps_path path,
-                                int variant, uint8_t *wsbase, hipStream_t s) {
+                                int variant, uint8_t *wsbase, hipStream_t s, bool capturing,
+                                bool d2h, bool host_only) {
   const Workspace ws = ws_view(P, wsbase);
   const Lib L = lib_view(lib);
   // scan phases in tiles of the single-query kernel and of the batched kernels
@@ -512,7 +554,9 @@ static fps_status launch_search(fps_library *lib, SearchCtx *ctx, Plan &P, fps_p
   std::vector<QBlock> bblocks, qblocks;
   std::vector<uint64_t> bitems, qitems;
   fps_make_blocks(&P, kBoundQBlock, tbb, &bblocks, &bitems);
-  const uint32_t qbs = path == FPS_PATH_MFMA_I8 ? mfma_qblock(variant) : (uint32_t)kPopQBlock;
+  const uint32_t qbs = path == FPS_PATH_MFMA_I8   ? mfma_qblock(variant)
+                       : path == FPS_PATH_MFMA_F4 ? mfma_f4_qblock(variant)
+                                                  : (uint32_t)kPopQBlock;
   fps_make_blocks(&P, qbs, tbb, &qblocks, &qitems);
   const uint32_t nqb = (uint32_t)qblocks.size();
   // parameter upload
@@ -525,13 +569,14 @@ static fps_status launch_search(fps_library *lib, SearchCtx *ctx, Plan &P, fps_p
   std::memcpy(h + P.off_qblocks, qblocks.data(), qblocks.size() * sizeof(QBlock));
   std::memcpy(h + P.off_qbitem, qitems.data(), qitems.size() * sizeof(uint64_t));
   std::memcpy(h + P.off_bblocks, bblocks.data(), bblocks.size() * sizeof(QBlock));
+  if (host_only) return FPS_OK;
   HIP_TRY(hipMemcpyAsync(wsbase, h, P.params_bytes, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipEventRecord(ctx->ev[0], s));
+  if ((rc = record(ctx->ev[0], s, capturing))) return rc;
   launch_prep(ws, P.q, (uint32_t)bblocks.size(), s);
   launch_bound(L, ws, (uint32_t)bblocks.size(), P.max_sample, s);
-  HIP_TRY(hipEventRecord(ctx->ev[1], s));
   for (size_t p = 0; p < nphases; ++p) {
     if (p > 0) launch_refine(ws, P.q, s);
+    if ((rc = record(ctx->ev[2 + 2 * p], s, capturing))) return rc;
     if (path == FPS_PATH_SINGLE) {
       for (uint32_t i = 0; i < P.q; ++i) {
         const QueryInfo &qi = P.qinfo[i];
@@ -546,15 +591,101 @@ static fps_status launch_search(fps_library *lib, SearchCtx *ctx, Plan &P, fps_p
       const uint64_t items = qitems[p * (nqb + 1) + nqb];
       if (path == FPS_PATH_POPCOUNT)
         launch_scan_popcount(L, ws, nqb, item_off, tbb[p], items, lib->cus, s);
+      else if (path == FPS_PATH_MFMA_F4)
+        launch_scan_mfma_f4(L, ws, nqb, item_off, tbb[p], items, lib->cus, variant, s);
       else
         launch_scan_mfma_i8(L, ws, nqb, item_off, tbb[p], items, lib->cus, variant, s);
     }
+    if ((rc = record(ctx->ev[3 + 2 * p], s, capturing))) return rc;
   }
+  ctx->last_phases = (uint32_t)nphases;
   HIP_TRY(hipGetLastError());
-  HIP_TRY(hipEventRecord(ctx->ev[2], s));
   launch_select(ws, P.q, s);
   HIP_TRY(hipGetLastError());
-  HIP_TRY(hipEventRecord(ctx->ev[3], s));
+  if ((rc = record(ctx->ev[1], s, capturing))) return rc;
+  if (d2h) {
+    if ((rc = ensure_pinned(&ctx->h_out, &ctx->h_out_bytes, back_bytes(P)))) return rc;
+    HIP_TRY(hipMemcpyAsync(ctx->h_out, wsbase + P.off_count, back_bytes(P), hipMemcpyDeviceToHost,
+                           s));
+  }
+  return FPS_OK;
+}
+
+// Everything a captured launch sequence depends on besides the parameter
+// block's contents: if two calls have equal keys, the same graph serves both.
+static std::vector<uint64_t> graph_key(const fps_library *lib, const SearchCtx *ctx,
+                                       const Plan &P, fps_path path, int variant,
+                                       const uint8_t *wsb) {
+  std::vector<uint64_t> k = {(uint64_t)(uintptr_t)wsb, (uint64_t)(uintptr_t)lib->dev,
+                             (uint64_t)(uintptr_t)ctx->h_params, (uint64_t)(uintptr_t)ctx->h_out,
+                             (uint64_t)path, (uint64_t)variant, P.q, P.params_bytes,
+                             P.total_bytes, P.max_sample, (uint64_t)lib->cus};
+  k.insert(k.end(), P.bounds.begin(), P.bounds.end());
+  for (const auto &rs : P.rsets) {
+    k.push_back(rs.mask);
+    k.push_back(rs.neff);
+  }
+  for (const auto &qi : P.qinfo) {
+    k.push_back(qi.keff);
+    k.push_back(qi.rset);
+    k.push_back(qi.cap);
+    k.push_back(qi.sample);
+  }
+  return k;
+}
+
+// Runs the launch sequence on stream s: replays a captured graph when the
+// launch shape matches one (up to kGraphs per context, least recently used
+// evicted), captures a graph when the shape was seen among the last kSeen
+// calls, and otherwise launches eagerly.
+static fps_status run_search(fps_library *lib, SearchCtx *ctx, Plan &P, fps_path path,
+                             int variant, uint8_t *wsb, hipStream_t s) {
+  fps_status rc;
+  if ((rc = ensure_pinned(&ctx->h_params, &ctx->h_params_bytes, P.params_bytes))) return rc;
+  if ((rc = ensure_pinned(&ctx->h_out, &ctx->h_out_bytes, back_bytes(P)))) return rc;
+  ctx->last.graph = 0;
+  // Graph replay serves the batched paths; for the single-query scan (a few
+  // launches around one long kernel) direct launches measured faster.
+  if (!lib->graphs || path == FPS_PATH_SINGLE)
+    return launch_search(lib, ctx, P, path, variant, wsb, s, false, true);
+  std::vector<uint64_t> key = graph_key(lib, ctx, P, path, variant, wsb);
+  for (size_t i = 0; i < ctx->graphs.size(); ++i) {
+    if (ctx->graphs[i].first != key) continue;
+    // same shape: refresh the parameter block on the host, replay the graph
+    if ((rc = launch_search(lib, ctx, P, path, variant, wsb, nullptr, false, false, true)))
+      return rc;
+    std::rotate(ctx->graphs.begin() + i, ctx->graphs.begin() + i + 1, ctx->graphs.end());
+    HIP_TRY(hipGraphLaunch(ctx->graphs.back().second, s));
+    ctx->last.graph = 1;
+    return FPS_OK;
+  }
+  if (std::find(ctx->seen.begin(), ctx->seen.end(), key) == ctx->seen.end()) {
+    ctx->seen.push_back(std::move(key));
+    if (ctx->seen.size() > SearchCtx::kSeen) ctx->seen.erase(ctx->seen.begin());
+    return launch_search(lib, ctx, P, path, variant, wsb, s, false, true);
+  }
+  // a recent shape again: capture it (on any capture failure, launch eagerly)
+  HIP_TRY(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+  rc = launch_search(lib, ctx, P, path, variant, wsb, ctx->cap, true, true);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(ctx->cap, &g);
+  hipGraphExec_t ex = nullptr;
+  hipError_t e2 = hipErrorUnknown;
+  if (!rc && e == hipSuccess && g) e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (rc || e != hipSuccess || e2 != hipSuccess) {
+    (void)hipGetLastError();
+    fps_clear_error();
+    ctx->graph_failures++;
+    return launch_search(lib, ctx, P, path, variant, wsb, s, false, true);
+  }
+  if (ctx->graphs.size() >= SearchCtx::kGraphs) {
+    (void)hipGraphExecDestroy(ctx->graphs.front().second);
+    ctx->graphs.erase(ctx->graphs.begin());
+  }
+  ctx->graphs.push_back({std::move(key), ex});
+  HIP_TRY(hipGraphLaunch(ex, s));
+  ctx->last.graph = 1;
   return FPS_OK;
 }
 
@@ -595,23 +726,32 @@ fps_status fps_search_impl(fps_library *lib, SearchCtx *ctx, const uint64_t *que
   rc = resolve_path(lib, ctx, P, forced, wsb, s, &path, &variant);
   if (rc) return rc;
   ctx->last.path = (uint32_t)path;
-  ctx->last.variant = path == FPS_PATH_MFMA_I8 ? (uint32_t)variant : 0u;
-  rc = launch_search(lib, ctx, P, path, variant, wsb, s);
+  ctx->last.variant =
+      path == FPS_PATH_MFMA_I8 || path == FPS_PATH_MFMA_F4 ? (uint32_t)variant : 0u;
+  rc = run_search(lib, ctx, P, path, variant, wsb, s);
   if (rc) return rc;
-  // per-query counts and flags and the hits come back in one copy
+  // per-query counts and flags and the hits came back in one copy
   const size_t out_bytes = P.total_out * sizeof(fps_hit);
-  const size_t back_bytes = P.off_out + out_bytes - P.off_count;
-  rc = ensure_pinned(&ctx->h_out, &ctx->h_out_bytes, back_bytes);
-  if (rc) return rc;
   uint8_t *ho = (uint8_t *)ctx->h_out;
   uint32_t *h_count = (uint32_t *)ho;
   uint32_t *h_flags = (uint32_t *)(ho + (P.off_flags - P.off_count));
   fps_hit *h_hits = (fps_hit *)(ho + (P.off_out - P.off_count));
-  HIP_TRY(hipMemcpyAsync(ho, wsb + P.off_count, back_bytes, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   float ms = 0;
-  if (hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]) == hipSuccess) ctx->last.scan_ms = ms;
-  if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[3]) == hipSuccess) ctx->last.total_ms = ms;
+  for (uint32_t p = 0; p < ctx->last_phases; ++p)
+    if (hipEventElapsedTime(&ms, ctx->ev[2 + 2 * p], ctx->ev[3 + 2 * p]) == hipSuccess)
+      ctx->last.scan_ms += ms;
+  if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess) ctx->last.total_ms = ms;
+  ctx->last.scan_launches = ctx->last_phases *
+                            (path == FPS_PATH_SINGLE ? (uint32_t)(P.q) : 1u);
+  ctx->sum_scan_ms += ctx->last.scan_ms;
+  ctx->sum_total_ms += ctx->last.total_ms;
+  ctx->sum_calls += 1;
+  ctx->sum_launches += ctx->last.scan_launches;
+  ctx->last.scan_ms_sum = ctx->sum_scan_ms;
+  ctx->last.total_ms_sum = ctx->sum_total_ms;
+  ctx->last.calls = ctx->sum_calls;
+  ctx->last.scan_launches_sum = ctx->sum_launches;
   const Workspace ws = ws_view(P, wsb);
   const Lib L = lib_view(lib);
   for (uint32_t i = 0; i < q; ++i) {
@@ -691,7 +831,7 @@ static void tune_load(fps_library *lib) {
     if (std::sscanf(line, "{\"cus\": %d, \"q_log2\": %d, \"k_log2\": %d, \"n_log2\": %d, \"path\": %d, "
                     "\"variant\": %d",
                     &cus, &q, &k, &n, &p, &v) == 6 &&
-        cus == lib->cus && p >= FPS_PATH_SINGLE && p <= FPS_PATH_MFMA_I8)
+        cus == lib->cus && p >= FPS_PATH_SINGLE && p <= FPS_PATH_MFMA_F4)
       lib->tuned[TuneKey{(uint32_t)q, (uint32_t)k, (uint32_t)n}] = {(fps_path)p, v};
   }
   std::fclose(f);
@@ -715,29 +855,30 @@ static std::vector<std::pair<fps_path, int>> tune_candidates(const Plan &P) {
   std::vector<std::pair<fps_path, int>> c;
   if (live <= 16) c.push_back({FPS_PATH_SINGLE, 0});
   c.push_back({FPS_PATH_POPCOUNT, 0});
-  if (live >= 8)
+  if (live >= 8) {
     for (int v = 0; v < mfma_variants(); ++v) c.push_back({FPS_PATH_MFMA_I8, v});
+    for (int v = 0; v < mfma_f4_variants(); ++v) c.push_back({FPS_PATH_MFMA_F4, v});
+  }
   return c;
 }
 
 static fps_status resolve_path(fps_library *lib, SearchCtx *ctx, Plan &P, fps_path requested,
                                uint8_t *wsb, hipStream_t s, fps_path *path, int *variant) {
-  *variant = lib->variant >= 0 ? lib->variant : 1;
-  if (requested != FPS_PATH_AUTO) {
-    *path = requested;
+  if (requested != FPS_PATH_AUTO || lib->path != FPS_PATH_AUTO) {
+    *path = requested != FPS_PATH_AUTO ? requested : lib->path;
+    // default tile shapes: 64 queries per wave, two waves per SIMD
+    const int nv = *path == FPS_PATH_MFMA_F4 ? mfma_f4_variants() : mfma_variants();
+    *variant = lib->variant >= 0 ? lib->variant % nv : (*path == FPS_PATH_MFMA_F4 ? 0 : 1);
     return FPS_OK;
   }
-  if (lib->path != FPS_PATH_AUTO) {
-    *path = lib->path == FPS_PATH_MFMA_F4 ? FPS_PATH_MFMA_I8 : lib->path;
-    return FPS_OK;
-  }
+  *variant = 0;
   const TuneKey key = tune_key(P);
   {
     std::lock_guard<std::mutex> lk(lib->tune_mu);
     auto it = lib->tuned.find(key);
     if (it != lib->tuned.end()) {
       *path = it->second.first;
-      if (lib->variant < 0) *variant = it->second.second;
+      *variant = it->second.second;
       return FPS_OK;
     }
   }
@@ -749,7 +890,7 @@ static fps_status resolve_path(fps_library *lib, SearchCtx *ctx, Plan &P, fps_pa
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(s));
     float ms = 0;
-    HIP_TRY(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[3]));
+    HIP_TRY(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
     if (ms < best) {
       best = ms;
       bp = cand.first;
@@ -762,6 +903,6 @@ static fps_status resolve_path(fps_library *lib, SearchCtx *ctx, Plan &P, fps_pa
   }
   tune_save(lib, key, bp, bv, best);
   *path = bp;
-  if (lib->variant < 0) *variant = bv;
+  *variant = bv;
   return FPS_OK;
 }

@@ -69,14 +69,14 @@ def test_batch_1024_full(paper_lib):
     lib_np, lib = paper_lib
     bq = fpsynth.batch_queries(lib_np, 1024, 1003)
     res = {}
-    for path in (fps.PATH_MFMA_I8, fps.PATH_POPCOUNT, fps.PATH_SINGLE):
+    for path in (fps.PATH_MFMA_I8, fps.PATH_MFMA_F4, fps.PATH_POPCOUNT, fps.PATH_SINGLE):
         say("case: full batch 1024 path", path)
         lib.set_path(path)
         res[path] = lib.search_batch(bq.words, 30)
         assert lib.last_stats()["path"] == fps.PATH_NAMES[path]
     lib.set_path(fps.PATH_AUTO)
     h0, o0 = res[fps.PATH_MFMA_I8]
-    for p in (fps.PATH_POPCOUNT, fps.PATH_SINGLE):
+    for p in (fps.PATH_MFMA_F4, fps.PATH_POPCOUNT, fps.PATH_SINGLE):
         assert np.array_equal(o0, res[p][1]) and np.array_equal(h0, res[p][0]), p
     properties(h0, o0, 30, None, fpsynth.PAPER_STRIDES)
     for i in range(0, 1024, 2):  # library-derived queries: nearest is within the flips
@@ -92,14 +92,14 @@ def test_uneven_4096_full(paper_lib):
     uq = fpsynth.batch_queries(lib_np, 4096, 1004).words
     k, m = fpsynth.uneven_params(4096, 1004)
     res = {}
-    for path in (fps.PATH_MFMA_I8, fps.PATH_POPCOUNT):
+    for path in (fps.PATH_MFMA_I8, fps.PATH_MFMA_F4, fps.PATH_POPCOUNT):
         say("case: full uneven 4096 path", path)
         lib.set_path(path)
         res[path] = lib.search_batch(uq, k, m)
     lib.set_path(fps.PATH_AUTO)
     h0, o0 = res[fps.PATH_MFMA_I8]
-    assert np.array_equal(o0, res[fps.PATH_POPCOUNT][1])
-    assert np.array_equal(h0, res[fps.PATH_POPCOUNT][0])
+    for p in (fps.PATH_MFMA_F4, fps.PATH_POPCOUNT):
+        assert np.array_equal(o0, res[p][1]) and np.array_equal(h0, res[p][0]), p
     properties(h0, o0, k, m, fpsynth.PAPER_STRIDES)
     picks = []
     for mask in fpsynth.MASK_CHOICES:

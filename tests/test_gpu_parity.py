@@ -12,7 +12,7 @@ torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
 
-PATHS = [fps.PATH_SINGLE, fps.PATH_POPCOUNT, fps.PATH_MFMA_I8]
+PATHS = [fps.PATH_SINGLE, fps.PATH_POPCOUNT, fps.PATH_MFMA_I8, fps.PATH_MFMA_F4]
 
 
 def say(*a):
@@ -85,8 +85,9 @@ def test_batch_paths_uneven_k_masks(small, path):
     check_batch(lib_np, lib, qs, k, masks, path, "uneven k and masks")
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
-def test_mfma_variants(small, variant):
+@pytest.mark.parametrize("path,variant", [(fps.PATH_MFMA_I8, v) for v in range(5)] +
+                         [(fps.PATH_MFMA_F4, v) for v in range(4)])
+def test_mfma_variants(small, path, variant):
     """Every matrix-core tile shape gives the oracle's answer (partial query
     blocks included: 600 queries over 3 masks)."""
     lib_np, lib = small
@@ -95,12 +96,51 @@ def test_mfma_variants(small, variant):
     k, masks = fpsynth.uneven_params(nq, 41)
     lib.set_variant(variant)
     try:
-        check_batch(lib_np, lib, qs, k, masks, fps.PATH_MFMA_I8, f"variant {variant}")
+        check_batch(lib_np, lib, qs, k, masks, path, f"variant {variant}")
         lib.set_tuning(sample_records=2048, phase_records=10_000)
-        check_batch(lib_np, lib, qs, k, masks, fps.PATH_MFMA_I8, f"variant {variant} 2-phase")
+        check_batch(lib_np, lib, qs, k, masks, path, f"variant {variant} 2-phase")
     finally:
         lib.set_tuning()
         lib.set_variant(-1)
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_graph_replay(small, path):
+    """A launch shape seen again is captured into a HIP graph and replayed with
+    new queries; every replay is checked against the oracle, with eager calls
+    of other shapes and synchronizations in between."""
+    lib_np, lib = small
+    nq = 200
+    k, masks = fpsynth.uneven_params(nq, 50)
+    lib.set_path(path)
+    used = []
+    try:
+        for rep in range(6):
+            qs = fpsynth.batch_queries(lib_np, nq, 600 + rep).words
+            say("case: graph replay", path, rep)
+            hits, off = lib.search_batch(qs, k, masks)
+            used.append(lib.last_stats()["graph"])
+            ohits, ooff = oracle.search_batch(lib_np.words, qs, k, lib.strides, masks)
+            assert np.array_equal(off, ooff) and np.array_equal(hits, ohits), rep
+            torch.cuda.synchronize()
+            one = lib.search(qs[1], 7, mask=3)
+            assert np.array_equal(one, oracle.search(lib_np.words, qs[1], 7,
+                                                     ranges=[(0, 75_000)])), rep
+    finally:
+        lib.set_path(fps.PATH_AUTO)
+    if path == fps.PATH_SINGLE:
+        assert not any(used), used  # the single-query scan launches directly
+    else:
+        assert used[0] is False and all(used[1:]), used
+    lib.set_graphs(False)
+    qs = fpsynth.batch_queries(lib_np, nq, 700).words
+    lib.set_path(path)
+    hits, off = lib.search_batch(qs, k, masks)
+    lib.set_path(fps.PATH_AUTO)
+    lib.set_graphs(True)
+    assert lib.last_stats()["graph"] is False
+    ohits, ooff = oracle.search_batch(lib_np.words, qs, k, lib.strides, masks)
+    assert np.array_equal(hits, ohits)
 
 
 def test_autotuner_and_cache(tmp_path, monkeypatch):
