@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, 8 TB/s
 INT8_PEAK_TOPS = 5000.0      # dense int8 MFMA, 5.0 POP/s
+FP4_PEAK_TFLOPS = 10100.0    # dense fp4 MFMA, 10.1 PFLOP/s
 ALGO_BYTES_PER_RECORD = 166 / 8   # 166 keys = 20.75 bytes of fingerprint
 LAYOUT_BYTES_PER_RECORD = 21      # as stored: u64 + u64 + u32 + u8
 ALGO_OPS_PER_PAIR = 2 * 166       # one multiply-add per key in the dot form
@@ -57,7 +58,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (counter calibration)")
-    ap.add_argument("--path", default="auto", help="batch path: auto|popcount|mfma_i8")
+    ap.add_argument("--path", default="auto", help="batch path: auto|popcount|mfma_i8|mfma_f4")
     return ap.parse_args()
 
 
@@ -103,14 +104,24 @@ def main():
         for i in range(W):
             lib.search(qs[i], 30)
         torch.cuda.synchronize()
-        st0 = lib.last_stats()
+        # the timed steps run untimed on the device (no HIP events) ...
         t = time.perf_counter()
         for i in range(W, W + K):
             lib.search(qs[i], 30)
         torch.cuda.synchronize()
         el = time.perf_counter() - t
-        st1 = lib.last_stats()
         ms = el * 1000 / K
+        # ... then the same queries again with HIP events around every kernel
+        # phase: the scan kernel's duration for the roofline
+        lib.set_timing(True)
+        st0 = lib.last_stats()
+        t = time.perf_counter()
+        for i in range(W, W + K):
+            lib.search(qs[i], 30)
+        torch.cuda.synchronize()
+        timed_ms = (time.perf_counter() - t) * 1000 / K
+        st1 = lib.last_stats()
+        lib.set_timing(False)
         scan_ms = st1["scan_ms_sum"] - st0["scan_ms_sum"]          # HIP events, scan launches
         launches = st1["scan_launches_sum"] - st0["scan_launches_sum"]
         dev_ms = (st1["total_ms_sum"] - st0["total_ms_sum"]) / K
@@ -124,6 +135,7 @@ def main():
             "scan_launches_per_query": launches / K,
             "scan_launch_avg_ms": scan_ms / max(1, launches),
             "device_ms_avg": dev_ms, "graph_replay": bool(st1["graph"]),
+            "ms_per_query_with_timing_events": timed_ms,
             "layout_gbs": layout, "layout_frac": layout / HBM_PEAK_GBS,
         }
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -135,10 +147,11 @@ def main():
 
     # ---------------- batch of 1024 ----------------
     path = {"auto": fps.PATH_AUTO, "popcount": fps.PATH_POPCOUNT,
-            "mfma_i8": fps.PATH_MFMA_I8}[args.path]
+            "mfma_i8": fps.PATH_MFMA_I8, "mfma_f4": fps.PATH_MFMA_F4}[args.path]
     if "batch" in legs:
         bq = fpsynth.batch_queries(lib_np, 1024, 1003).words
         lib.set_path(path)
+        lib.set_timing(True)  # events cost microseconds against a multi-ms batch
         for _ in range(2):  # first sight: autotuner; second: graph capture
             lib.search_batch(bq, 30)
         torch.cuda.synchronize()
@@ -158,12 +171,18 @@ def main():
              "graph_replay": scans[-1]["graph"]}
         if single:
             b["speedup_vs_single_qps"] = b["qps"] / single["qps"]
-        if scans[-1]["path"] == "mfma_i8":
+        if scans[-1]["path"] in ("mfma_i8", "mfma_f4"):
+            # Algorithmic operations: one multiply-add per key per pair; each path
+            # is priced against the dense peak of its own MFMA data type.
             tops = ALGO_OPS_PER_PAIR * pairs / (scan * 1e-3) / 1e12
-            b["roofline"] = {"bound": "mfma", "achieved": tops, "peak": INT8_PEAK_TOPS,
-                             "unit": "TOP/s", "frac": tops / INT8_PEAK_TOPS}
+            i8 = scans[-1]["path"] == "mfma_i8"
+            peak = INT8_PEAK_TOPS if i8 else FP4_PEAK_TFLOPS
+            b["roofline"] = {"bound": "mfma", "achieved": tops, "peak": peak,
+                             "unit": "TOP/s" if i8 else "TFLOP/s", "frac": tops / peak,
+                             "dtype": "i8" if i8 else "fp4"}
         out["batch"] = b
         lib.set_path(fps.PATH_AUTO)
+        lib.set_timing(False)
         log("batch:", json.dumps(b))
 
     # ---------------- uneven 4096 ----------------
@@ -171,6 +190,7 @@ def main():
         uq = fpsynth.batch_queries(lib_np, 4096, 1004).words
         uk, um = fpsynth.uneven_params(4096, 1004)
         lib.set_path(path)
+        lib.set_timing(True)
         for _ in range(2):
             lib.search_batch(uq, uk, um)
         times, scans = [], []
@@ -188,6 +208,7 @@ def main():
              "fallbacks": scans[-1]["fallbacks"]}
         out["uneven"] = u
         lib.set_path(fps.PATH_AUTO)
+        lib.set_timing(False)
         log("uneven:", json.dumps(u))
 
     # ---------------- serving ----------------

@@ -128,6 +128,14 @@ fps_status fps_set_path(fps_library *lib, fps_path path);
  * enable = 0 launches every kernel directly. */
 fps_status fps_set_graphs(fps_library *lib, int enable);
 
+/* Device timing of searches (scan_ms, total_ms and their sums in
+ * fps_search_stats).  Off by default: the timing events cost about 10
+ * microseconds of a single-query search, whose first kernels wait on the
+ * host.  enable != 0 stamps HIP events at the first kernel, around every scan
+ * phase and at the last kernel of every call.  The autotuner times its
+ * candidates regardless.  Errors: FPS_E_ARG. */
+fps_status fps_set_timing(fps_library *lib, int enable);
+
 /* Selects the tile shape of the matrix-core kernel: 0 = 64 queries per wave,
  * 1 = 64 per wave with two waves per SIMD, 2 = 128 per wave, 3 = 32 per wave
  * with two waves per SIMD, 4 = 64 queries shared by a block's four waves,
@@ -191,8 +199,9 @@ typedef struct {
   uint32_t fallbacks;     /* queries answered by the exact two-pass fallback */
   uint32_t variant;       /* matrix-core tile shape used (fps_set_variant) */
   uint64_t candidates;    /* candidates appended by the scan, summed over queries */
-  double scan_ms;         /* device time of the scan kernel launches of the call (HIP events) */
-  double total_ms;        /* device time from the first to the last kernel */
+  double scan_ms;         /* device time of the scan kernel launches of the call (HIP
+                             events; 0 unless fps_set_timing enabled them) */
+  double total_ms;        /* device time from the first to the last kernel (likewise) */
   uint32_t graph;         /* 1 if the launch sequence was replayed from a HIP graph */
   uint32_t scan_launches; /* scan kernel launches of the call */
   /* running sums over every call on this handle (or server slot) */
@@ -213,8 +222,9 @@ fps_status fps_last_search_stats(const fps_library *lib, fps_search_stats *stats
  *   the default; tiny values force the overflow fallback).
  * sample_records:  records per query whose distance histogram gives the first
  *   bound (0 = default 2^16).
- * phase_records:   records per query scanned before the bound is refined from
- *   the candidates found so far (0 = default 2^22).
+ * phase_records:   records per query scanned before the bound is first
+ *   refined from the candidates found so far (0 = sample_records times the
+ *   geometric phase ratio, which is 4096 / max k clamped to 8..64).
  * force_fallback:  nonzero answers every query with the exact two-pass path.
  * Results never depend on these; workspace sizes do: query
  * fps_workspace_bytes after setting them.

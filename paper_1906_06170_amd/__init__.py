@@ -79,6 +79,7 @@ EXPORTS = {
     "fps_set_path": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "fps_set_variant": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "fps_set_graphs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "fps_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "fps_workspace_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_void_p]),
     "fps_search": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
@@ -133,10 +134,15 @@ def _ptr(a: np.ndarray):
     return ctypes.c_void_p(a.ctypes.data)
 
 
-def _stream(stream):
+def _stream(stream, device: int | None = None):
+    """HIP stream handle: the given torch stream, else torch's current stream
+    on `device` (the raw-stream query is the cheap form of current_stream())."""
     import torch
-    s = torch.cuda.current_stream() if stream is None else stream
-    return ctypes.c_void_p(s.cuda_stream)
+    if stream is not None:
+        return ctypes.c_void_p(stream.cuda_stream)
+    if device is not None and hasattr(torch._C, "_cuda_getCurrentRawStream"):
+        return ctypes.c_void_p(torch._C._cuda_getCurrentRawStream(device))
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
 def _require_gpu():
@@ -169,6 +175,7 @@ class Library:
         self.n = int(w.shape[0])
         nbytes = int(c.fps_library_device_bytes(self.n))
         self._buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self._device = self._buf.device.index
         self._ws = None
         self._ws_sizes = {}
         self._handle = ctypes.c_void_p()
@@ -225,6 +232,11 @@ class Library:
         """Replay repeated launch shapes from HIP graphs (default on)."""
         _check(load_library().fps_set_graphs(self._handle, int(bool(enable))))
 
+    def set_timing(self, enable: bool):
+        """Device timing (scan_ms, total_ms in last_stats) with HIP events;
+        off by default, since the events lengthen a single-query search."""
+        _check(load_library().fps_set_timing(self._handle, int(bool(enable))))
+
     def set_variant(self, variant: int):
         """Matrix-core tile shape (0..3, or -1 for the tuner's choice)."""
         _check(load_library().fps_set_variant(self._handle, int(variant)))
@@ -265,7 +277,7 @@ class Library:
         nout = ctypes.c_uint32()
         _check(load_library().fps_search(self._handle, _ptr(q), int(k), int(mask),
                                          ctypes.c_void_p(ws.data_ptr()), ws.numel(), _ptr(out),
-                                         ctypes.byref(nout), _stream(stream)))
+                                         ctypes.byref(nout), _stream(stream, self._device)))
         return out[:nout.value].copy()
 
     def search_batch(self, queries, k, mask=None, stream=None):
@@ -286,7 +298,7 @@ class Library:
         _check(load_library().fps_search_batch(
             self._handle, _ptr(qs), nq, _ptr(kk), None if mm is None else _ptr(mm),
             ctypes.c_void_p(ws.data_ptr()), ws.numel(), _ptr(out), cap, _ptr(off),
-            _stream(stream)))
+            _stream(stream, self._device)))
         return out[:int(off[-1])].copy(), off
 
 

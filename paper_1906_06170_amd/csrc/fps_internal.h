@@ -11,6 +11,7 @@
 // distance) is the popcount of a^a' + b^b' + c^c' + d^d'.  Queries are relabeled
 // the same way on the host.  Records [n, Np) are zero and never reported.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -29,11 +30,18 @@ constexpr int kFbWaves = kFbBlocks * 4;
 
 constexpr int kScanTile = 512;      // records per wave iteration of the single-query scan
 constexpr int kBatchTile = 2048;    // records per work item of the batched kernels
-constexpr int kBoundChunk = 1024;   // records per block of the bound kernel
+constexpr int kBoundChunk = 1024;   // least records per block of the bound kernel
+constexpr int kBoundBlocks = 128;   // most blocks per query block of the bound kernel
 constexpr int kHistCopies = 8;      // bound histograms are spread over 8 copies per query
 constexpr uint64_t kDefaultBoundSample = 1ull << 16;  // records of the bound sample
+// One scan phase when the first bound is expected to admit at most this many
+// records per query (keff * neff / sample); more phases otherwise.
+constexpr uint64_t kSinglePhaseAppends = 8192;
 constexpr uint64_t kDefaultPhaseA = 0;  // first phase length in records (0 = from the schedule)
 constexpr int kMaxPhases = 12;          // scan phases (the bound is refined between phases)
+constexpr uint32_t kSegments = 64;      // candidate segments of a query in a small batch
+constexpr uint32_t kSegQueries = 16;    // batches up to this size use kSegments segments
+constexpr uint32_t kCtrStride = 32;     // counters of a segmented query, 128 bytes apart
 
 // A union of record ranges (the strides one mask selects), in ascending order,
 // adjacent strides merged.  Virtual index v in [0, neff) enumerates its records
@@ -56,10 +64,14 @@ struct QueryInfo {
   uint32_t keff;      // min(k, neff)
   uint32_t rset;      // RangeSet index
   uint64_t cand_off;  // first candidate slot
-  uint32_t cap;       // candidate slots
+  uint32_t cap;       // candidate slots: nseg * segcap (+ spillcap when nseg > 1)
   uint32_t popc;      // keys set in the query
   uint64_t out_off;   // first output hit
   uint64_t sample;    // records used for the bound: min(sample_records, neff)
+  uint32_t nseg;      // candidate segments (1 or kSegments)
+  uint32_t segcap;    // slots per segment
+  uint32_t spillcap;  // slots of the spill area (nseg > 1)
+  uint32_t ctr_off;   // first counter in Workspace::ctr (segment s at + s * kCtrStride)
 };
 
 // A block of queries sharing one RangeSet (indices into the permutation).
@@ -79,7 +91,8 @@ struct Workspace {
   QBlock *bblocks;      // for the bound kernel (<= kBoundQBlock queries each)
   uint32_t *bdone;      // per bound block: finished chunk blocks
   uint32_t *T;          // per-query distance bound (int32; -1 = no candidate wanted)
-  uint32_t *count;      // per-query candidates appended (exact even past cap)
+  uint32_t *ctr;        // candidate counters (see QueryInfo::ctr_off)
+  uint32_t *count;      // per-query valid candidates, written by select (statistics)
   uint32_t *flags;      // per-query: 1 overflow, 2 too many ties for LDS sort, 4 bound failed
   uint32_t *hist;       // per query: kHistCopies x kBins histogram of the bound sample
   uint64_t *cand;       // candidates: (distance << 32) | index
@@ -96,32 +109,64 @@ struct Lib {
   uint64_t n, np;
 };
 
+// Timing events of a launch.  They are stamped by the kernel dispatch itself
+// (no marker packets between kernels); both null: an untimed launch.
+struct LaunchEv {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+};
+
+template <typename F, typename... Args>
+inline void launch_k(F kernel, dim3 grid, dim3 block, hipStream_t s, const LaunchEv &ev,
+                     Args... args) {
+  hipExtLaunchKernelGGL(kernel, grid, block, 0u, s, ev.start, ev.stop, 0u, args...);
+}
+
 // ---- launchers (kernels.hip) ----
-void launch_prep(const Workspace &ws, uint32_t q, uint32_t nbblocks, hipStream_t s);
+void launch_prep(const Workspace &ws, uint32_t q, uint32_t nbblocks, uint32_t nctr,
+                 hipStream_t s, const LaunchEv &ev);
+// A parameter block small enough to travel as a kernel argument: the prep
+// kernel copies it to dst (the workspace), which saves a host-to-device copy.
+constexpr size_t kInlineParams = 3072;
+struct InlineParams {
+  uint64_t bytes;
+  uint64_t w[kInlineParams / 8];
+};
+void launch_prep_inline(const Workspace &ws, uint32_t q, uint32_t nbblocks, uint32_t nctr,
+                        uint8_t *dst, const InlineParams &p, hipStream_t s,
+                        const LaunchEv &ev);
 void launch_bound(const Lib &lib, const Workspace &ws, uint32_t nbblocks, uint64_t max_sample,
                   hipStream_t s);
 void launch_refine(const Workspace &ws, uint32_t q, hipStream_t s);
 void launch_scan_single(const Lib &lib, const Workspace &ws, uint32_t qidx, uint64_t t_begin,
-                        uint64_t t_end, int cus, hipStream_t s);
+                        uint64_t t_end, int cus, hipStream_t s, const LaunchEv &ev);
 // Batched scans: work items are the tiles [tile_lo, tile_hi) of every query
 // block's range (clamped to its tile count); item_off is the phase's nqb + 1
 // prefix of items per query block.
 void launch_scan_popcount(const Lib &lib, const Workspace &ws, uint32_t nqb,
                           const uint64_t *item_off, uint64_t tile_lo, uint64_t items, int cus,
-                          hipStream_t s);
-void launch_select(const Workspace &ws, uint32_t q, hipStream_t s);
+                          hipStream_t s, const LaunchEv &ev);
+// Where select also writes the per-query counts and flags and the hits: the
+// device addresses of pinned host buffers (all null: the workspace only).
+struct HostBack {
+  uint32_t *count;
+  uint32_t *flags;
+  fps_hit *hits;
+};
+void launch_select(const Workspace &ws, uint32_t q, const HostBack &hb, hipStream_t s,
+                   const LaunchEv &ev);
 void launch_fallback(const Lib &lib, const Workspace &ws, uint32_t qidx, uint64_t neff,
                      hipStream_t s);
 // ---- launchers (mfma.hip) ----
 void launch_scan_mfma_i8(const Lib &lib, const Workspace &ws, uint32_t nqb,
                          const uint64_t *item_off, uint64_t tile_lo, uint64_t items, int cus,
-                         int variant, hipStream_t s);
+                         int variant, hipStream_t s, const LaunchEv &ev);
 int mfma_variants();
 uint32_t mfma_qblock(int variant);
 // ---- launchers (mfma_f4.hip) ----
 void launch_scan_mfma_f4(const Lib &lib, const Workspace &ws, uint32_t nqb,
                          const uint64_t *item_off, uint64_t tile_lo, uint64_t items, int cus,
-                         int variant, hipStream_t s);
+                         int variant, hipStream_t s, const LaunchEv &ev);
 int mfma_f4_variants();
 uint32_t mfma_f4_qblock(int variant);
 

@@ -18,16 +18,10 @@
 //      with d <= D_k are sorted by (d, index) in LDS and the first k are kept.
 // A query whose candidates overflow their buffer, or whose ties at D_k exceed
 // the LDS sort, is answered by an exact two-pass ordered fallback.
+#include "cand.h"
 #include "fps_internal.h"
 
 namespace fps {
-
-__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63; }
-
-__device__ __forceinline__ uint32_t rank_below(uint64_t mask) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
 
 // Global record index of virtual index v of a RangeSet.
 __device__ __forceinline__ uint64_t v2g(const RangeSet *rs, uint64_t v) {
@@ -57,28 +51,14 @@ __device__ __forceinline__ uint32_t dist_rec(const Rec &r, const QueryInfo *q) {
   return dist4(r.a, r.b, r.c, r.d, q->qa, q->qb, q->qc, q->qd);
 }
 
-// Appends key for every lane with hit set: one atomic per wave.
-__device__ __forceinline__ void wave_append(bool hit, uint64_t key, uint32_t *cnt, uint64_t *cand,
-                                            uint32_t cap) {
-  const uint64_t bal = __ballot(hit);
-  if (bal == 0) return;
-  const uint32_t lane = lane_id();
-  const uint32_t leader = (uint32_t)__ffsll((unsigned long long)bal) - 1;
-  uint32_t base = 0;
-  if (lane == leader) base = atomicAdd(cnt, (uint32_t)__popcll(bal));
-  base = __shfl(base, (int)leader);
-  if (hit) {
-    const uint32_t pos = base + rank_below(bal);
-    if (pos < cap) cand[pos] = key;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Clears the per-query counters and histograms (a fill kernel, so the sequence
 // can be captured into a graph).
 // ---------------------------------------------------------------------------
-__global__ void k_prep(Workspace ws, uint32_t q, uint32_t nbblocks) {
+__device__ __forceinline__ void prep_body(const Workspace &ws, uint32_t q, uint32_t nbblocks,
+                                          uint32_t nctr) {
   const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nctr; i += stride) ws.ctr[i] = 0;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < q; i += stride) {
     ws.count[i] = 0;
     ws.flags[i] = 0;
@@ -91,42 +71,82 @@ __global__ void k_prep(Workspace ws, uint32_t q, uint32_t nbblocks) {
     ws.hist[i] = 0;
 }
 
-void launch_prep(const Workspace &ws, uint32_t q, uint32_t nbblocks, hipStream_t s) {
+__global__ void k_prep(Workspace ws, uint32_t q, uint32_t nbblocks, uint32_t nctr) {
+  prep_body(ws, q, nbblocks, nctr);
+}
+
+__global__ void k_prep_inline(Workspace ws, uint32_t q, uint32_t nbblocks, uint32_t nctr,
+                              uint64_t *dst, InlineParams p) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < p.bytes / 8; i += stride)
+    dst[i] = p.w[i];
+  prep_body(ws, q, nbblocks, nctr);
+}
+
+static uint32_t prep_blocks(uint32_t q) {
   uint32_t blocks = (q * kHistCopies * kBins + 255) / 256;
   if (blocks > 1024) blocks = 1024;
   if (blocks == 0) blocks = 1;
-  hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(256), 0, s, ws, q, nbblocks);
+  return blocks;
+}
+
+void launch_prep(const Workspace &ws, uint32_t q, uint32_t nbblocks, uint32_t nctr,
+                 hipStream_t s, const LaunchEv &ev) {
+  launch_k(k_prep, dim3(prep_blocks(q)), dim3(256), s, ev, ws, q, nbblocks, nctr);
+}
+
+void launch_prep_inline(const Workspace &ws, uint32_t q, uint32_t nbblocks, uint32_t nctr,
+                        uint8_t *dst, const InlineParams &p, hipStream_t s,
+                        const LaunchEv &ev) {
+  launch_k(k_prep_inline, dim3(prep_blocks(q)), dim3(256), s, ev, ws, q, nbblocks, nctr,
+           (uint64_t *)dst, p);
 }
 
 // ---------------------------------------------------------------------------
 // Bound: distance histogram of the first `sample` records of each query's
-// range.  Grid: x = 1024-record chunk, y = block of <= 32 queries sharing a
-// range.  Blocks add their histograms into one of 8 copies per query (spreading
-// the atomics); the last chunk block of a query block to finish sums the copies
-// and sets T1 = smallest t whose cumulative sample count reaches keff (166 when
-// the sample holds fewer than keff records, so every record passes).
+// range.  Grid: x = chunk of `chunk` records, y = block of <= 32 queries
+// sharing a range.  Blocks add their histograms into one of 8 copies per query
+// (spreading the atomics); the last chunk block of a query block to finish sums
+// the copies and sets T1 = smallest t whose cumulative sample count reaches
+// keff (166 when the sample holds fewer than keff records, so every record
+// passes).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_bound(Lib lib, Workspace ws) {
+__global__ __launch_bounds__(256) void k_bound(Lib lib, Workspace ws, uint32_t chunk) {
   __shared__ uint32_t h[kBoundQBlock * kBins];
   __shared__ QueryInfo qs[kBoundQBlock];
   __shared__ uint32_t s_last;
   const QBlock bb = ws.bblocks[blockIdx.y];
   const RangeSet *rs = ws.rsets + bb.rset;
   const uint64_t sample = ws.qinfo[ws.perm[bb.first]].sample;
-  const uint64_t v0 = (uint64_t)blockIdx.x * kBoundChunk;
+  const uint64_t v0 = (uint64_t)blockIdx.x * chunk;
   const uint32_t tid = threadIdx.x;
   const uint32_t copy = blockIdx.x % kHistCopies;
   if (v0 < sample) {
-    const uint64_t v1 = min(v0 + (uint64_t)kBoundChunk, sample);
+    const uint64_t v1 = min(v0 + (uint64_t)chunk, sample);
     for (uint32_t i = tid; i < bb.count * kBins; i += blockDim.x) h[i] = 0;
     for (uint32_t i = tid; i < bb.count; i += blockDim.x) qs[i] = ws.qinfo[ws.perm[bb.first + i]];
     __syncthreads();
+    // the chunk [v0, v1) of virtual indices, range by range; 8 records per
+    // thread in flight
+    const uint32_t nr = rs->nranges;
+    for (uint32_t r = 0; r < nr; ++r) {
+      const uint64_t a = max(v0, rs->voff[r]), b = min(v1, rs->voff[r + 1]);
+      if (a >= b) continue;
+      const uint64_t gofs = rs->begin[r] - rs->voff[r];  // global index = v + gofs
+      for (uint64_t vb = a; vb < b; vb += 256 * 8) {
+        Rec rec[8];
+        bool ok[8];
 #pragma unroll
-    for (int u = 0; u < kBoundChunk / 256; ++u) {
-      const uint64_t v = v0 + 256 * u + tid;
-      if (v < v1) {
-        const Rec r = load_rec(lib, v2g(rs, v));
-        for (uint32_t j = 0; j < bb.count; ++j) atomicAdd(&h[j * kBins + dist_rec(r, &qs[j])], 1u);
+        for (int u = 0; u < 8; ++u) {
+          const uint64_t v = vb + 256 * u + tid;
+          ok[u] = v < b;
+          if (ok[u]) rec[u] = load_rec(lib, v + gofs);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (ok[u])
+            for (uint32_t j = 0; j < bb.count; ++j)
+              atomicAdd(&h[j * kBins + dist_rec(rec[u], &qs[j])], 1u);
       }
     }
     __syncthreads();
@@ -154,27 +174,26 @@ __global__ __launch_bounds__(256) void k_bound(Lib lib, Workspace ws) {
     h[i] = x;
   }
   __syncthreads();
-  for (uint32_t j = tid; j < bb.count; j += blockDim.x) {
+  // one wave per query (wave-uniform loop)
+  for (uint32_t j = tid >> 6; j < bb.count; j += blockDim.x >> 6) {
     const uint32_t q = ws.perm[bb.first + j];
     const uint32_t keff = ws.qinfo[q].keff;
-    uint32_t T = (uint32_t)kKeys, cum = 0;
-    for (uint32_t t = 0; t <= (uint32_t)kKeys; ++t) {
-      cum += h[j * kBins + t];
-      if (cum >= keff) {
-        T = t;
-        break;
-      }
-    }
-    ws.T[q] = T;
+    uint32_t cum;
+    uint32_t T = wave_kth(h + j * kBins, (uint32_t)kKeys, keff, &cum);
+    if (T == 0xFFFFFFFFu) T = (uint32_t)kKeys;
+    if (lane_id() == 0) ws.T[q] = T;
   }
 }
 
 void launch_bound(const Lib &lib, const Workspace &ws, uint32_t nbblocks, uint64_t max_sample,
                   hipStream_t s) {
   if (nbblocks == 0) return;
-  uint32_t chunks = (uint32_t)((max_sample + kBoundChunk - 1) / kBoundChunk);
+  // up to kBoundBlocks chunks of at least kBoundChunk records
+  uint64_t chunk = (max_sample + kBoundBlocks - 1) / kBoundBlocks;
+  chunk = (chunk + kBoundChunk - 1) / kBoundChunk * kBoundChunk;
+  uint32_t chunks = (uint32_t)((max_sample + chunk - 1) / chunk);
   if (chunks == 0) chunks = 1;
-  hipLaunchKernelGGL(k_bound, dim3(chunks, nbblocks), dim3(256), 0, s, lib, ws);
+  hipLaunchKernelGGL(k_bound, dim3(chunks, nbblocks), dim3(256), 0, s, lib, ws, (uint32_t)chunk);
 }
 
 // ---------------------------------------------------------------------------
@@ -184,35 +203,32 @@ void launch_bound(const Lib &lib, const Workspace &ws, uint32_t nbblocks, uint64
 // bound.  One block per query.  A query whose buffer overflowed keeps its bound
 // (it is answered by the fallback anyway).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_refine(Workspace ws) {
+__global__ __launch_bounds__(1024) void k_refine(Workspace ws) {
   __shared__ uint32_t hist[kBins];
+  __shared__ uint32_t m[kSegments + 1];
+  __shared__ uint32_t s_total, s_over;
   const uint32_t q = blockIdx.x, tid = threadIdx.x;
   const QueryInfo *qi = ws.qinfo + q;
   const uint32_t keff = qi->keff;
   if (keff == 0) return;
-  const uint32_t n = ws.count[q];
-  if (n > qi->cap) return;
-  const uint64_t *cand = ws.cand + qi->cand_off;
   for (uint32_t i = tid; i < kBins; i += blockDim.x) hist[i] = 0;
+  cand_counts(ws, qi, m, &s_total, &s_over);
+  if (s_over) return;
+  cand_for_each(ws, qi, m, [&](uint64_t key) { atomicAdd(&hist[(uint32_t)(key >> 32)], 1u); });
   __syncthreads();
-  for (uint32_t i = tid; i < n; i += blockDim.x) atomicAdd(&hist[(uint32_t)(cand[i] >> 32)], 1u);
-  __syncthreads();
-  if (tid == 0) {
-    uint32_t cum = 0;
+  if (tid < 64) {
     const int32_t T1 = (int32_t)ws.T[q];
-    for (int32_t t = 0; t < T1; ++t) {
-      cum += hist[t];
-      if (cum >= keff) {
-        ws.T[q] = (uint32_t)t;
-        break;
-      }
+    if (T1 > 0) {
+      uint32_t cum;
+      const uint32_t t = wave_kth(hist, (uint32_t)(T1 - 1), keff, &cum);
+      if (t != 0xFFFFFFFFu && tid == 0) ws.T[q] = t;
     }
   }
 }
 
 void launch_refine(const Workspace &ws, uint32_t q, hipStream_t s) {
   if (q == 0) return;
-  hipLaunchKernelGGL(k_refine, dim3(q), dim3(256), 0, s, ws);
+  hipLaunchKernelGGL(k_refine, dim3(q), dim3(1024), 0, s, ws);
 }
 
 // ---------------------------------------------------------------------------
@@ -232,17 +248,25 @@ __global__ __launch_bounds__(256) void k_scan_single(Lib lib, Workspace ws, uint
   const uint32_t qc = qi->qc, qd = qi->qd;
   const int32_t T = (int32_t)ws.T[qidx];
   const RangeSet *rs = ws.rsets + qi->rset;
-  uint32_t *cnt = ws.count + qidx;
-  uint64_t *cand = ws.cand + qi->cand_off;
-  const uint32_t cap = qi->cap;
   const uint32_t lane = lane_id();
-  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  // wave-uniform (scalar) tile loop: the range bookkeeping stays in SGPRs
+  const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wib;
   const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  uint32_t r = 0;
-  for (uint64_t t = t_begin + wave; t < t_end; t += nwaves) {
-    while (t >= rs->t1off[r + 1]) ++r;
-    const uint64_t rb = rs->begin[r], re = rs->end[r];
-    const uint64_t base = (rb & ~(uint64_t)(kScanTile - 1)) + (t - rs->t1off[r]) * kScanTile;
+  const uint32_t seg = (uint32_t)(wave % qi->nseg);
+  const uint32_t nranges = rs->nranges;
+  // Tiles t = t_begin + wave + j * nwaves, walked range by range so that the
+  // range table is read once per range, not per tile.
+  for (uint32_t r = 0; r < nranges; ++r) {
+  const uint64_t r0 = rs->t1off[r], r1 = rs->t1off[r + 1];
+  const uint64_t lo = r0 > t_begin ? r0 : t_begin, hi = r1 < t_end ? r1 : t_end;
+  if (lo >= hi) continue;
+  const uint64_t rb = rs->begin[r], re = rs->end[r];
+  const uint64_t tile0 = (rb & ~(uint64_t)(kScanTile - 1)) - r0 * kScanTile;
+  const uint64_t skip = (lo - t_begin) % nwaves;  // first t >= lo of this wave's sequence
+  for (uint64_t t = lo + (wave >= skip ? wave - skip : wave + nwaves - skip); t < hi;
+       t += nwaves) {
+    const uint64_t base = tile0 + t * kScanTile;
     u64x2 A[4], B[4];
     uint64_t C[4];
     uint32_t D[4];
@@ -254,29 +278,46 @@ __global__ __launch_bounds__(256) void k_scan_single(Lib lib, Workspace ws, uint
       C[u] = __builtin_nontemporal_load(reinterpret_cast<const uint64_t *>(lib.c + i));
       D[u] = __builtin_nontemporal_load(reinterpret_cast<const uint16_t *>(lib.d + i));
     }
+    // Distances of the lane's 8 records; the tile's hits take one reservation.
+    uint32_t dist[8];
+    bool hit[8];
+    uint64_t bal[8];
+    uint32_t tot = 0;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const uint64_t i = base + 128 * u + 2 * lane;
-      const int32_t d0 =
-          (int32_t)dist4(A[u].x, B[u].x, (uint32_t)C[u], D[u] & 0xFFu, qa, qb, qc, qd);
-      const int32_t d1 =
-          (int32_t)dist4(A[u].y, B[u].y, (uint32_t)(C[u] >> 32), D[u] >> 8, qa, qb, qc, qd);
-      const bool h0 = d0 <= T && i >= rb && i < re;
-      const bool h1 = d1 <= T && i + 1 >= rb && i + 1 < re;
-      wave_append(h0, ((uint64_t)d0 << 32) | i, cnt, cand, cap);
-      wave_append(h1, ((uint64_t)d1 << 32) | (i + 1), cnt, cand, cap);
+      dist[2 * u] = dist4(A[u].x, B[u].x, (uint32_t)C[u], D[u] & 0xFFu, qa, qb, qc, qd);
+      dist[2 * u + 1] =
+          dist4(A[u].y, B[u].y, (uint32_t)(C[u] >> 32), D[u] >> 8, qa, qb, qc, qd);
+      hit[2 * u] = (int32_t)dist[2 * u] <= T && i >= rb && i < re;
+      hit[2 * u + 1] = (int32_t)dist[2 * u + 1] <= T && i + 1 >= rb && i + 1 < re;
+      bal[2 * u] = __ballot(hit[2 * u]);
+      bal[2 * u + 1] = __ballot(hit[2 * u + 1]);
+      tot += (uint32_t)(__popcll(bal[2 * u]) + __popcll(bal[2 * u + 1]));
     }
+    if (tot == 0) continue;
+    Resv rv{0, 0};
+    if (lane == 0) rv = cand_reserve(ws, qi, seg, tot);
+    rv.base = __shfl(rv.base, 0);
+    rv.sbase = __shfl(rv.sbase, 0);
+    uint32_t p = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint64_t i = base + 128 * (j >> 1) + 2 * lane + (j & 1);
+      if (hit[j]) cand_put(ws, qi, seg, rv, p + rank_below(bal[j]), ((uint64_t)dist[j] << 32) | i);
+      p += (uint32_t)__popcll(bal[j]);
+    }
+  }
   }
 }
 
 void launch_scan_single(const Lib &lib, const Workspace &ws, uint32_t qidx, uint64_t t_begin,
-                        uint64_t t_end, int cus, hipStream_t s) {
+                        uint64_t t_end, int cus, hipStream_t s, const LaunchEv &ev) {
   if (t_end <= t_begin) return;
   uint64_t blocks = (t_end - t_begin + 3) / 4;  // 4 waves per block
   const uint64_t maxb = (uint64_t)cus * 32;
   if (blocks > maxb) blocks = maxb;
-  hipLaunchKernelGGL(k_scan_single, dim3((uint32_t)blocks), dim3(256), 0, s, lib, ws, qidx,
-                     t_begin, t_end);
+  launch_k(k_scan_single, dim3((uint32_t)blocks), dim3(256), s, ev, lib, ws, qidx, t_begin, t_end);
 }
 
 // ---------------------------------------------------------------------------
@@ -342,13 +383,13 @@ __global__ __launch_bounds__(256) void k_scan_popcount(Lib lib, Workspace ws, ui
         if (__ballot(any < 0) == 0) continue;
         const uint32_t q = qid[j];
         const QueryInfo *qi = ws.qinfo + q;
+        const uint32_t seg = blockIdx.x % qi->nseg;
         const int32_t T1 = -seed;  // T + 1
 #pragma unroll
         for (int u = 0; u < kPopRL; ++u) {
           const uint64_t g = sub + 256 * u + tid;
           const bool hit = ok[u] && v[u] < 0;
-          wave_append(hit, ((uint64_t)(uint32_t)(v[u] + T1) << 32) | g, ws.count + q,
-                      ws.cand + qi->cand_off, qi->cap);
+          wave_append(hit, ((uint64_t)(uint32_t)(v[u] + T1) << 32) | g, ws, qi, seg);
         }
       }
     }
@@ -357,64 +398,143 @@ __global__ __launch_bounds__(256) void k_scan_popcount(Lib lib, Workspace ws, ui
 
 void launch_scan_popcount(const Lib &lib, const Workspace &ws, uint32_t nqb,
                           const uint64_t *item_off, uint64_t tile_lo, uint64_t items, int cus,
-                          hipStream_t s) {
+                          hipStream_t s, const LaunchEv &ev) {
   if (items == 0) return;
   uint64_t blocks = items;
   const uint64_t maxb = (uint64_t)cus * 8;
   if (blocks > maxb) blocks = maxb;
-  hipLaunchKernelGGL(k_scan_popcount, dim3((uint32_t)blocks), dim3(256), 0, s, lib, ws, nqb,
-                     item_off, tile_lo, items);
+  launch_k(k_scan_popcount, dim3((uint32_t)blocks), dim3(256), s, ev, lib, ws, nqb, item_off,
+           tile_lo, items);
 }
 
 // ---------------------------------------------------------------------------
-// Select: one block per query.
+// Select: one block of 1024 threads per query.  A 167-bin histogram of the
+// candidates gives D_k and the number m of candidates with d <= D_k.  Up to
+// kSortCap candidates are staged in LDS during the histogram pass, so the
+// buffer is read from memory once.  m <= kRankCap: each of the m keys is
+// ranked directly by counting the smaller ones (the keys (d << 32) | index are
+// unique); larger m: a bitonic sort in LDS.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_select(Workspace ws) {
+constexpr uint32_t kRankCap = 1024;
+
+// A slot for every active lane from an LDS counter: one atomic per wave.
+__device__ __forceinline__ uint32_t wave_slot(uint32_t *ctr) {
+  const uint64_t act = __ballot(1);
+  const uint32_t leader = (uint32_t)__ffsll((unsigned long long)act) - 1;
+  uint32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(ctr, (uint32_t)__popcll(act));
+  base = __shfl(base, (int)leader);
+  return base + rank_below(act);
+}
+
+__device__ __forceinline__ fps_hit hit_of(uint64_t key) {
+  fps_hit h;
+  h.index = (uint32_t)key;
+  h.distance = (uint32_t)(key >> 32);
+  return h;
+}
+
+__global__ __launch_bounds__(1024) void k_select(Workspace ws, HostBack hb) {
   __shared__ uint32_t hist[kBins];
   __shared__ uint64_t keys[kSortCap];
-  __shared__ uint32_t s_dk, s_fail, s_ncoll;
+  __shared__ uint64_t rk[kRankCap];
+  __shared__ uint32_t s_dk, s_fail, s_m, s_ncoll, s_nstage;
+  __shared__ uint32_t segn[kSegments + 1];
+  __shared__ uint32_t s_total, s_over;
   const uint32_t q = blockIdx.x;
   const QueryInfo *qi = ws.qinfo + q;
   const uint32_t keff = qi->keff;
   const uint32_t tid = threadIdx.x;
-  if (keff == 0) return;
-  const uint32_t n = ws.count[q];
-  if (n > qi->cap) {
-    if (tid == 0) ws.flags[q] |= 1u;
+  if (keff == 0) {
+    if (tid == 0 && hb.count) {
+      hb.count[q] = 0;
+      hb.flags[q] = 0;
+    }
     return;
   }
-  const uint64_t *cand = ws.cand + qi->cand_off;
   for (uint32_t i = tid; i < kBins; i += blockDim.x) hist[i] = 0;
-  __syncthreads();
-  for (uint32_t i = tid; i < n; i += blockDim.x) atomicAdd(&hist[(uint32_t)(cand[i] >> 32)], 1u);
-  __syncthreads();
   if (tid == 0) {
-    uint32_t cum = 0, dk = 0xFFFFFFFFu;
-    for (uint32_t t = 0; t <= (uint32_t)kKeys; ++t) {
-      cum += hist[t];
-      if (cum >= keff) {
-        dk = t;
-        break;
-      }
-    }
-    s_fail = 0;
-    if (dk == 0xFFFFFFFFu) s_fail = 4u;
-    else if (cum > kSortCap) s_fail = 2u;
-    s_dk = dk;
     s_ncoll = 0;
+    s_nstage = 0;
+  }
+  const uint32_t n = cand_counts(ws, qi, segn, &s_total, &s_over);
+  if (tid == 0) {
+    ws.count[q] = n;
+    if (hb.count) hb.count[q] = n;
+  }
+  if (s_over) {
+    if (tid == 0) {
+      ws.flags[q] |= 1u;
+      if (hb.flags) hb.flags[q] = ws.flags[q];
+    }
+    return;
+  }
+  const bool staged = n <= kSortCap;
+  cand_for_each(ws, qi, segn, [&](uint64_t key) {
+    atomicAdd(&hist[(uint32_t)(key >> 32)], 1u);
+    if (staged) keys[wave_slot(&s_nstage)] = key;
+  });
+  __syncthreads();
+  if (tid < 64) {
+    uint32_t cum;
+    const uint32_t dk = wave_kth(hist, (uint32_t)kKeys, keff, &cum);
+    if (tid == 0) {
+      s_fail = dk == 0xFFFFFFFFu ? 4u : (cum > kSortCap ? 2u : 0u);
+      s_dk = dk;
+      s_m = cum;
+    }
   }
   __syncthreads();
   if (s_fail) {
-    if (tid == 0) ws.flags[q] |= s_fail;
+    if (tid == 0) {
+      ws.flags[q] |= s_fail;
+      if (hb.flags) hb.flags[q] = ws.flags[q];
+    }
     return;
   }
-  const uint32_t dk = s_dk;
-  for (uint32_t i = tid; i < n; i += blockDim.x) {
-    const uint64_t key = cand[i];
-    if ((uint32_t)(key >> 32) <= dk) keys[atomicAdd(&s_ncoll, 1u)] = key;
+  if (tid == 0 && hb.flags) hb.flags[q] = ws.flags[q];
+  const uint32_t dk = s_dk, m = s_m;
+  fps_hit *out = (hb.hits ? hb.hits : ws.out) + qi->out_off;
+  if (m <= kRankCap) {
+    if (staged) {
+      for (uint32_t i = tid; i < n; i += blockDim.x) {
+        const uint64_t key = keys[i];
+        if ((uint32_t)(key >> 32) <= dk) rk[wave_slot(&s_ncoll)] = key;
+      }
+    } else {
+      cand_for_each(ws, qi, segn, [&](uint64_t key) {
+        if ((uint32_t)(key >> 32) <= dk) rk[wave_slot(&s_ncoll)] = key;
+      });
+    }
+    __syncthreads();
+    if (tid < m) {
+      const uint64_t key = rk[tid];
+      uint32_t r = 0;
+      for (uint32_t j = 0; j < m; ++j) r += rk[j] < key ? 1u : 0u;
+      if (r < keff) out[r] = hit_of(key);
+    }
+    return;
+  }
+  // m > kRankCap: gather the keys with d <= D_k into keys[] (in place when
+  // staged: every thread first takes its share into registers) and sort
+  if (staged) {
+    constexpr int kPer = kSortCap / 1024;
+    uint64_t mine[kPer];
+#pragma unroll
+    for (int c = 0; c < kPer; ++c) {
+      const uint32_t i = tid + 1024u * c;
+      mine[c] = i < n ? keys[i] : ~0ull;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kPer; ++c)
+      if (tid + 1024u * c < n && (uint32_t)(mine[c] >> 32) <= dk) keys[wave_slot(&s_ncoll)] = mine[c];
+  } else {
+    cand_for_each(ws, qi, segn, [&](uint64_t key) {
+      if ((uint32_t)(key >> 32) <= dk) keys[wave_slot(&s_ncoll)] = key;
+    });
   }
   __syncthreads();
-  const uint32_t m = s_ncoll;
   uint32_t P = 1;
   while (P < m) P <<= 1;
   for (uint32_t i = m + tid; i < P; i += blockDim.x) keys[i] = ~0ull;
@@ -435,17 +555,13 @@ __global__ __launch_bounds__(1024) void k_select(Workspace ws) {
       __syncthreads();
     }
   }
-  fps_hit *out = ws.out + qi->out_off;
-  for (uint32_t i = tid; i < keff; i += blockDim.x) {
-    const uint64_t key = keys[i];
-    out[i].index = (uint32_t)key;
-    out[i].distance = (uint32_t)(key >> 32);
-  }
+  for (uint32_t i = tid; i < keff; i += blockDim.x) out[i] = hit_of(keys[i]);
 }
 
-void launch_select(const Workspace &ws, uint32_t q, hipStream_t s) {
+void launch_select(const Workspace &ws, uint32_t q, const HostBack &hb, hipStream_t s,
+                   const LaunchEv &ev) {
   if (q == 0) return;
-  hipLaunchKernelGGL(k_select, dim3(q), dim3(1024), 0, s, ws);
+  launch_k(k_select, dim3(q), dim3(1024), s, ev, ws, hb);
 }
 
 // ---------------------------------------------------------------------------

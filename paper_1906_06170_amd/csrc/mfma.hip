@@ -159,19 +159,20 @@ __device__ __forceinline__ void decode(const Workspace &ws, const QBlock &qb, co
       const uint64_t bal = __ballot(hit);
       if (bal == 0) continue;
       const uint32_t mine = (uint32_t)(bal >> (32 * half));
-      uint32_t base = 0;
+      Resv rv{0, 0};
       uint32_t q = 0;
       if (mine) q = ws.perm[qb.first + row];
+      const QueryInfo *qi = ws.qinfo + q;
+      const uint32_t seg = blockIdx.x % (mine ? qi->nseg : 1u);
       if (mine && (lane & 31) == (uint32_t)(__ffs(mine) - 1))
-        base = atomicAdd(ws.count + q, (uint32_t)__popc(mine));
+        rv = cand_reserve(ws, qi, seg, (uint32_t)__popc(mine));
       // leader of each half: its lowest hit lane
       const uint32_t lead = mine ? 32 * half + (uint32_t)(__ffs(mine) - 1) : lane;
-      base = __shfl(base, (int)lead);
+      rv.base = __shfl(rv.base, (int)lead);
+      rv.sbase = __shfl(rv.sbase, (int)lead);
       if (hit) {
-        const QueryInfo *qi = ws.qinfo + q;
-        const uint32_t pos = base + (uint32_t)__popc(mine & below);
         const uint32_t d = (uint32_t)(u + (int32_t)ws.T[q] + 1);
-        if (pos < qi->cap) ws.cand[qi->cand_off + pos] = ((uint64_t)d << 32) | g;
+        cand_put(ws, qi, seg, rv, (uint32_t)__popc(mine & below), ((uint64_t)d << 32) | g);
       }
     }
   }
@@ -305,7 +306,7 @@ uint32_t mfma_qblock(int variant) {
 
 void launch_scan_mfma_i8(const Lib &lib, const Workspace &ws, uint32_t nqb,
                          const uint64_t *item_off, uint64_t tile_lo, uint64_t items, int cus,
-                         int variant, hipStream_t s) {
+                         int variant, hipStream_t s, const LaunchEv &ev) {
   if (items == 0) return;
   const int per_cu = variant == 1 || variant == 3 || variant == 4 ? 2 : 1;
   uint64_t blocks = (uint64_t)cus * per_cu;
@@ -314,8 +315,8 @@ void launch_scan_mfma_i8(const Lib &lib, const Workspace &ws, uint32_t nqb,
   blocks = (items + per - 1) / per;
   const dim3 g((uint32_t)blocks), b(256);
 #define FPS_MFMA_LAUNCH(MQ, WPE, COLS)                                                     \
-  hipLaunchKernelGGL((k_scan_mfma_i8<MQ, WPE, COLS>), g, b, 0, s, lib, ws, nqb, item_off, \
-                     tile_lo, items, per)
+  launch_k((k_scan_mfma_i8<MQ, WPE, COLS>), g, b, s, ev, lib, ws, nqb, item_off, tile_lo, items, \
+           per)
   switch (variant) {
     case 1: FPS_MFMA_LAUNCH(2, 2, false); break;
     case 2: FPS_MFMA_LAUNCH(4, 1, false); break;

@@ -5,6 +5,7 @@
 // kSub records; the records of a stage are held in registers (one record per
 // two threads) before they are expanded into LDS.
 #pragma once
+#include "cand.h"
 #include "fps_internal.h"
 
 namespace fps {

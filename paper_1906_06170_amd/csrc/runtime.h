@@ -17,11 +17,16 @@ struct SearchCtx {
   size_t h_params_bytes = 0;
   void *h_out = nullptr;
   size_t h_out_bytes = 0;
+  void *h_out_dev = nullptr;     // device address of h_out (null: not mapped)
+  const void *h_out_dev_of = nullptr;  // the h_out that h_out_dev belongs to
   // ev[0]/ev[1]: first and last kernel of a call; ev[2 + 2p], ev[3 + 2p]:
   // around the scan launches of phase p
   hipEvent_t ev[2 + 2 * fps::kMaxPhases] = {};
   fps_search_stats last{};
-  uint32_t last_phases = 0;
+  uint32_t last_phases = 0;    // scan phases of the last launch sequence
+  uint32_t last_timed = 0;     // bit p: the events around phase p were stamped
+  uint32_t last_launches = 0;  // scan kernel launches of the last sequence
+  bool last_total_timed = false;  // ev[0], ev[1] were stamped
   double sum_scan_ms = 0, sum_total_ms = 0;  // running sums since creation
   uint64_t sum_calls = 0, sum_launches = 0;
   // graph replay of repeated launch shapes (see run_search)
@@ -53,6 +58,7 @@ struct fps_library {
   uint64_t sample = fps::kDefaultBoundSample;  // records of the bound sample
   uint64_t phase_a = fps::kDefaultPhaseA;      // first phase boundary (0 = from the schedule)
   int force_fb = 0;
+  bool timing = false;  // HIP events around the kernels of every call
   bool graphs = true;  // capture and replay repeated launch shapes
   SearchCtx ctx;  // staging of direct calls on this handle
   std::mutex tune_mu;
@@ -66,10 +72,10 @@ struct Plan {
   std::vector<fps::QueryInfo> qinfo;
   std::vector<uint32_t> perm;
   std::vector<uint64_t> bounds;  // scan phase boundaries in records (last = UINT64_MAX)
-  uint64_t total_cand = 0, total_out = 0, max_sample = 0;
+  uint64_t total_cand = 0, total_out = 0, max_sample = 0, total_ctr = 0;
   size_t off_rsets = 0, off_qinfo = 0, off_perm = 0, off_qblocks = 0, off_qbitem = 0,
          off_bblocks = 0, params_bytes = 0;
-  size_t off_bdone = 0, off_T = 0, off_count = 0, off_flags = 0, off_hist = 0, off_cand = 0, off_out = 0,
+  size_t off_bdone = 0, off_T = 0, off_ctr = 0, off_count = 0, off_flags = 0, off_hist = 0, off_cand = 0, off_out = 0,
          off_fbh = 0, off_fbo = 0, off_fbt = 0, total_bytes = 0;
 };
 

@@ -238,6 +238,13 @@ extern "C" fps_status fps_set_graphs(fps_library *lib, int enable) {
   return FPS_OK;
 }
 
+extern "C" fps_status fps_set_timing(fps_library *lib, int enable) {
+  fps_clear_error();
+  if (!lib) return fps_fail(FPS_E_ARG, "NULL library");
+  lib->timing = enable != 0;
+  return FPS_OK;
+}
+
 extern "C" fps_status fps_set_variant(fps_library *lib, int variant) {
   fps_clear_error();
   if (!lib) return fps_fail(FPS_E_ARG, "NULL library");
@@ -311,18 +318,25 @@ fps_status fps_make_rangeset(const fps_library *lib, uint32_t mask, RangeSet *rs
   return FPS_OK;
 }
 
-// Scan phases.  The first bound comes from a sample of S1 records; the scan then
-// proceeds in phases whose boundaries grow geometrically (b1 = G * S1, b2 =
-// G * b1, ...), and after each phase the bound is refined to the keff-th
-// smallest distance of the prefix scanned so far.  A phase [b_i, b_i+1) then
-// appends about keff * (b_i+1 - b_i) / b_i records, times a small factor for
-// ties at the bound; G = 4096 / keff (clamped to 8..64) keeps that near a few
-// thousand per query.
+// Scan phases.  The first bound comes from a sample of S1 records.  When it is
+// expected to admit few records (keff * neff / S1 <= kSinglePhaseAppends, at
+// the largest keff and neff of the batch) one phase scans everything.
+// Otherwise the scan proceeds in phases whose boundaries grow geometrically
+// (b1 = G * S1, b2 = G * b1, ...), and after each phase the bound is refined to
+// the keff-th smallest distance of the prefix scanned so far.  A phase
+// [b_i, b_i+1) then appends about keff * (b_i+1 - b_i) / b_i records, times a
+// small factor for ties at the bound; G = 4096 / keff (clamped to 8..64) keeps
+// that near a few thousand per query.
 static std::vector<uint64_t> phase_bounds(const fps_library *lib, uint64_t max_neff,
-                                          uint64_t max_keff) {
+                                          uint64_t max_keff, uint64_t s1) {
   std::vector<uint64_t> b{0};
+  s1 = std::max<uint64_t>(s1, 1);
+  if (!lib->phase_a && (double)max_keff * (double)max_neff <= (double)kSinglePhaseAppends * s1) {
+    b.push_back(UINT64_MAX);
+    return b;
+  }
   const uint64_t G = std::min<uint64_t>(64, std::max<uint64_t>(8, 4096 / std::max<uint64_t>(max_keff, 1)));
-  uint64_t a = lib->phase_a ? lib->phase_a : std::max<uint64_t>(lib->sample, 1) * G;
+  uint64_t a = lib->phase_a ? lib->phase_a : s1 * G;
   while (a < max_neff && b.size() < (size_t)kMaxPhases) {
     b.push_back(a);
     a = a > (UINT64_MAX / G) ? UINT64_MAX : a * G;
@@ -359,6 +373,7 @@ fps_status fps_plan(const fps_library *lib, uint32_t q, const uint32_t *k, const
   P->total_cand = 0;
   P->total_out = 0;
   P->max_sample = 0;
+  P->total_ctr = 0;
   std::vector<uint32_t> rs_of(q);
   for (uint32_t i = 0; i < q; ++i) {
     const uint32_t m = mask ? mask[i] : FPS_MASK_ALL;
@@ -383,14 +398,29 @@ fps_status fps_plan(const fps_library *lib, uint32_t q, const uint32_t *k, const
     if (keff) max_neff = std::max(max_neff, neff);
     max_keff = std::max(max_keff, keff);
   }
-  P->bounds = phase_bounds(lib, max_neff, max_keff);
+  const uint64_t s1 = lib->sample;
+  P->bounds = phase_bounds(lib, max_neff, max_keff, s1);
   for (uint32_t i = 0; i < q; ++i) {
     const RangeSet &rs = P->rsets[rs_of[i]];
     QueryInfo &qi = P->qinfo[i];
     qi.rset = rs_of[i];
     qi.keff = (uint32_t)std::min<uint64_t>(k[i], rs.neff);
-    qi.sample = std::min<uint64_t>(lib->sample, rs.neff);
-    qi.cap = capacity(lib, P->bounds, qi.keff, rs.neff, qi.sample);
+    qi.sample = std::min<uint64_t>(s1, rs.neff);
+    const uint32_t base_cap = capacity(lib, P->bounds, qi.keff, rs.neff, qi.sample);
+    // Small batches: kSegments segments sharing base_cap, plus a spill area of
+    // base_cap (appends are spread over the segments' counters).
+    qi.nseg = (q <= kSegQueries && qi.keff > 0) ? kSegments : 1u;
+    if (qi.nseg > 1) {
+      qi.segcap = (base_cap + kSegments - 1) / kSegments;
+      qi.spillcap = base_cap;
+      qi.cap = qi.nseg * qi.segcap + qi.spillcap;
+    } else {
+      qi.segcap = base_cap;
+      qi.spillcap = 0;
+      qi.cap = base_cap;
+    }
+    qi.ctr_off = (uint32_t)P->total_ctr;
+    P->total_ctr += qi.nseg > 1 ? (uint64_t)(qi.nseg + 1) * kCtrStride : 1u;
     qi.cand_off = P->total_cand;
     qi.out_off = P->total_out;
     P->total_cand += qi.cap;
@@ -404,16 +434,25 @@ fps_status fps_plan(const fps_library *lib, uint32_t q, const uint32_t *k, const
     off = align_up(off + bytes, 256);
     return o;
   };
+  // the parameter region is packed (16-byte fields) so that a small plan fits
+  // a kernel argument
+  auto take16 = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes, 16);
+    return o;
+  };
   const size_t maxqb = (size_t)q + P->rsets.size() + 1;
-  P->off_rsets = take(P->rsets.size() * sizeof(RangeSet));
-  P->off_qinfo = take((size_t)q * sizeof(QueryInfo));
-  P->off_perm = take((size_t)q * sizeof(uint32_t));
-  P->off_qblocks = take(maxqb * sizeof(QBlock));
-  P->off_qbitem = take((size_t)kMaxPhases * (maxqb + 1) * sizeof(uint64_t));
-  P->off_bblocks = take(maxqb * sizeof(QBlock));
+  P->off_rsets = take16(P->rsets.size() * sizeof(RangeSet));
+  P->off_qinfo = take16((size_t)q * sizeof(QueryInfo));
+  P->off_perm = take16((size_t)q * sizeof(uint32_t));
+  P->off_qblocks = take16(maxqb * sizeof(QBlock));
+  P->off_qbitem = take16((size_t)kMaxPhases * (maxqb + 1) * sizeof(uint64_t));
+  P->off_bblocks = take16(maxqb * sizeof(QBlock));
   P->params_bytes = off;
+  off = align_up(off, 256);
   P->off_bdone = take(maxqb * 4);
   P->off_T = take((size_t)q * 4);
+  P->off_ctr = take(P->total_ctr * 4);
   P->off_hist = take((size_t)q * kHistCopies * kBins * 4);
   P->off_cand = take(P->total_cand * sizeof(uint64_t));
   // count, flags and the hits are contiguous: one copy brings them back
@@ -489,6 +528,7 @@ static Workspace ws_view(const Plan &P, uint8_t *base) {
   w.bblocks = (QBlock *)(base + P.off_bblocks);
   w.bdone = (uint32_t *)(base + P.off_bdone);
   w.T = (uint32_t *)(base + P.off_T);
+  w.ctr = (uint32_t *)(base + P.off_ctr);
   w.count = (uint32_t *)(base + P.off_count);
   w.flags = (uint32_t *)(base + P.off_flags);
   w.hist = (uint32_t *)(base + P.off_hist);
@@ -501,7 +541,7 @@ static Workspace ws_view(const Plan &P, uint8_t *base) {
 }
 
 static fps_status launch_search(fps_library *lib, SearchCtx *ctx, Plan &P, fps_path path,
-                                int variant, uint8_t *wsbase, hipStream_t s,
+                                int variant, uint8_t *wsbase, hipStream_t s, bool timed,
                                 bool capturing = false, bool d2h = false, bool host_only = false);
 static fps_status resolve_path(fps_library *lib, SearchCtx *ctx, Plan &P, fps_path requested,
                                uint8_t *wsb, hipStream_t s, fps_path *path, int *variant);
@@ -538,8 +578,8 @@ static size_t back_bytes(const Plan &P) {
 // with d2h the copy of counts, flags and hits into the pinned staging.  Also
 // used under stream capture (capturing = true) to record a graph.
 static fps_status launch_search(fps_library *lib, SearchCtx *ctx, Plan &P, fps_path path,
-                                int variant, uint8_t *wsbase, hipStream_t s, bool capturing,
-                                bool d2h, bool host_only) {
+                                int variant, uint8_t *wsbase, hipStream_t s, bool timed,
+                                bool capturing, bool d2h, bool host_only) {
   const Workspace ws = ws_view(P, wsbase);
   const Lib L = lib_view(lib);
   // scan phases in tiles of the single-query kernel and of the batched kernels
@@ -569,41 +609,98 @@ static fps_status launch_search(fps_library *lib, SearchCtx *ctx, Plan &P, fps_p
   std::memcpy(h + P.off_qblocks, qblocks.data(), qblocks.size() * sizeof(QBlock));
   std::memcpy(h + P.off_qbitem, qitems.data(), qitems.size() * sizeof(uint64_t));
   std::memcpy(h + P.off_bblocks, bblocks.data(), bblocks.size() * sizeof(QBlock));
-  if (host_only) return FPS_OK;
-  HIP_TRY(hipMemcpyAsync(wsbase, h, P.params_bytes, hipMemcpyHostToDevice, s));
-  if ((rc = record(ctx->ev[0], s, capturing))) return rc;
-  launch_prep(ws, P.q, (uint32_t)bblocks.size(), s);
-  launch_bound(L, ws, (uint32_t)bblocks.size(), P.max_sample, s);
+  // Scan launches of every phase: the single path launches once per query whose
+  // range reaches into the phase, the batched paths once per nonempty phase.
+  std::vector<std::vector<uint32_t>> phase_q(nphases);
+  ctx->last_phases = (uint32_t)nphases;
+  ctx->last_launches = 0;
+  ctx->last_timed = 0;
   for (size_t p = 0; p < nphases; ++p) {
-    if (p > 0) launch_refine(ws, P.q, s);
-    if ((rc = record(ctx->ev[2 + 2 * p], s, capturing))) return rc;
+    uint32_t n = 0;
     if (path == FPS_PATH_SINGLE) {
       for (uint32_t i = 0; i < P.q; ++i) {
         const QueryInfo &qi = P.qinfo[i];
-        if (qi.keff == 0) continue;
         const RangeSet &rs = P.rsets[qi.rset];
         const uint64_t tiles = rs.t1off[rs.nranges];
-        launch_scan_single(L, ws, i, std::min(t1b[p], tiles), std::min(t1b[p + 1], tiles),
-                           lib->cus, s);
+        if (qi.keff && std::min(t1b[p + 1], tiles) > std::min(t1b[p], tiles))
+          phase_q[p].push_back(i);
+      }
+      n = (uint32_t)phase_q[p].size();
+    } else {
+      n = qitems[p * (nqb + 1) + nqb] > 0 ? 1u : 0u;
+    }
+    ctx->last_launches += n;
+    // eager launches stamp the events of a phase only if it launches; a graph
+    // holds event nodes for every phase
+    if (timed && (n > 0 || capturing || host_only)) ctx->last_timed |= 1u << p;
+  }
+  ctx->last_total_timed = timed;
+  if (host_only) return FPS_OK;
+  // Direct mode (eager launches of a small plan): the parameter block travels
+  // as an argument of the prep kernel and select writes counts, flags and hits
+  // straight into the pinned staging buffer -- no copy commands on the stream.
+  // Graph replays need the copies (their kernel arguments are frozen).
+  const bool direct = !capturing && d2h && P.params_bytes <= kInlineParams &&
+                      back_bytes(P) <= ctx->h_out_bytes && ctx->h_out_dev;
+  HostBack hb{nullptr, nullptr, nullptr};
+  // Eager launches carry their timing events (stamped by the dispatches, no
+  // marker packets); under capture the events are graph nodes.
+  const LaunchEv none{};
+  const bool mark = timed && capturing;  // event nodes of a graph
+  const bool stamp = timed && !capturing;  // events carried by eager launches
+  if (mark && (rc = record(ctx->ev[0], s, true))) return rc;
+  const LaunchEv ev_first = stamp ? LaunchEv{ctx->ev[0], nullptr} : none;
+  if (direct) {
+    InlineParams ip;
+    ip.bytes = align_up(P.params_bytes, 8);
+    std::memcpy(ip.w, h, ip.bytes);
+    launch_prep_inline(ws, P.q, (uint32_t)bblocks.size(), (uint32_t)P.total_ctr, wsbase, ip, s,
+                       ev_first);
+    uint8_t *hd = (uint8_t *)ctx->h_out_dev;
+    hb.count = (uint32_t *)hd;
+    hb.flags = (uint32_t *)(hd + (P.off_flags - P.off_count));
+    hb.hits = (fps_hit *)(hd + (P.off_out - P.off_count));
+  } else {
+    HIP_TRY(hipMemcpyAsync(wsbase, h, P.params_bytes, hipMemcpyHostToDevice, s));
+    launch_prep(ws, P.q, (uint32_t)bblocks.size(), (uint32_t)P.total_ctr, s, ev_first);
+  }
+  launch_bound(L, ws, (uint32_t)bblocks.size(), P.max_sample, s);
+  for (size_t p = 0; p < nphases; ++p) {
+    if (p > 0) launch_refine(ws, P.q, s);
+    hipEvent_t e0 = ctx->ev[2 + 2 * p], e1 = ctx->ev[3 + 2 * p];
+    if (mark && (rc = record(e0, s, true))) return rc;
+    if (path == FPS_PATH_SINGLE) {
+      const std::vector<uint32_t> &qs = phase_q[p];
+      for (size_t j = 0; j < qs.size(); ++j) {
+        const QueryInfo &qi = P.qinfo[qs[j]];
+        const RangeSet &rs = P.rsets[qi.rset];
+        const uint64_t tiles = rs.t1off[rs.nranges];
+        LaunchEv e{};
+        if (stamp) {
+          if (j == 0) e.start = e0;
+          if (j + 1 == qs.size()) e.stop = e1;
+        }
+        launch_scan_single(L, ws, qs[j], std::min(t1b[p], tiles), std::min(t1b[p + 1], tiles),
+                           lib->cus, s, e);
       }
     } else {
       const uint64_t *item_off = ws.qb_item + p * (nqb + 1);
       const uint64_t items = qitems[p * (nqb + 1) + nqb];
+      const LaunchEv e = stamp ? LaunchEv{e0, e1} : none;
       if (path == FPS_PATH_POPCOUNT)
-        launch_scan_popcount(L, ws, nqb, item_off, tbb[p], items, lib->cus, s);
+        launch_scan_popcount(L, ws, nqb, item_off, tbb[p], items, lib->cus, s, e);
       else if (path == FPS_PATH_MFMA_F4)
-        launch_scan_mfma_f4(L, ws, nqb, item_off, tbb[p], items, lib->cus, variant, s);
+        launch_scan_mfma_f4(L, ws, nqb, item_off, tbb[p], items, lib->cus, variant, s, e);
       else
-        launch_scan_mfma_i8(L, ws, nqb, item_off, tbb[p], items, lib->cus, variant, s);
+        launch_scan_mfma_i8(L, ws, nqb, item_off, tbb[p], items, lib->cus, variant, s, e);
     }
-    if ((rc = record(ctx->ev[3 + 2 * p], s, capturing))) return rc;
+    if (mark && (rc = record(e1, s, true))) return rc;
   }
-  ctx->last_phases = (uint32_t)nphases;
   HIP_TRY(hipGetLastError());
-  launch_select(ws, P.q, s);
+  launch_select(ws, P.q, hb, s, stamp ? LaunchEv{nullptr, ctx->ev[1]} : none);
   HIP_TRY(hipGetLastError());
-  if ((rc = record(ctx->ev[1], s, capturing))) return rc;
-  if (d2h) {
+  if (mark && (rc = record(ctx->ev[1], s, true))) return rc;
+  if (d2h && !direct) {
     if ((rc = ensure_pinned(&ctx->h_out, &ctx->h_out_bytes, back_bytes(P)))) return rc;
     HIP_TRY(hipMemcpyAsync(ctx->h_out, wsbase + P.off_count, back_bytes(P), hipMemcpyDeviceToHost,
                            s));
@@ -616,7 +713,8 @@ static fps_status launch_search(fps_library *lib, SearchCtx *ctx, Plan &P, fps_p
 static std::vector<uint64_t> graph_key(const fps_library *lib, const SearchCtx *ctx,
                                        const Plan &P, fps_path path, int variant,
                                        const uint8_t *wsb) {
-  std::vector<uint64_t> k = {(uint64_t)(uintptr_t)wsb, (uint64_t)(uintptr_t)lib->dev,
+  std::vector<uint64_t> k = {(uint64_t)lib->timing, (uint64_t)(uintptr_t)wsb,
+                             (uint64_t)(uintptr_t)lib->dev,
                              (uint64_t)(uintptr_t)ctx->h_params, (uint64_t)(uintptr_t)ctx->h_out,
                              (uint64_t)path, (uint64_t)variant, P.q, P.params_bytes,
                              P.total_bytes, P.max_sample, (uint64_t)lib->cus};
@@ -643,16 +741,23 @@ static fps_status run_search(fps_library *lib, SearchCtx *ctx, Plan &P, fps_path
   fps_status rc;
   if ((rc = ensure_pinned(&ctx->h_params, &ctx->h_params_bytes, P.params_bytes))) return rc;
   if ((rc = ensure_pinned(&ctx->h_out, &ctx->h_out_bytes, back_bytes(P)))) return rc;
+  if (ctx->h_out_dev_of != ctx->h_out) {
+    void *d = nullptr;
+    ctx->h_out_dev = hipHostGetDevicePointer(&d, ctx->h_out, 0) == hipSuccess ? d : nullptr;
+    (void)hipGetLastError();
+    ctx->h_out_dev_of = ctx->h_out;
+  }
   ctx->last.graph = 0;
   // Graph replay serves the batched paths; for the single-query scan (a few
   // launches around one long kernel) direct launches measured faster.
   if (!lib->graphs || path == FPS_PATH_SINGLE)
-    return launch_search(lib, ctx, P, path, variant, wsb, s, false, true);
+    return launch_search(lib, ctx, P, path, variant, wsb, s, lib->timing, false, true);
   std::vector<uint64_t> key = graph_key(lib, ctx, P, path, variant, wsb);
   for (size_t i = 0; i < ctx->graphs.size(); ++i) {
     if (ctx->graphs[i].first != key) continue;
     // same shape: refresh the parameter block on the host, replay the graph
-    if ((rc = launch_search(lib, ctx, P, path, variant, wsb, nullptr, false, false, true)))
+    if ((rc = launch_search(lib, ctx, P, path, variant, wsb, nullptr, lib->timing, false, false,
+                            true)))
       return rc;
     std::rotate(ctx->graphs.begin() + i, ctx->graphs.begin() + i + 1, ctx->graphs.end());
     HIP_TRY(hipGraphLaunch(ctx->graphs.back().second, s));
@@ -662,11 +767,11 @@ static fps_status run_search(fps_library *lib, SearchCtx *ctx, Plan &P, fps_path
   if (std::find(ctx->seen.begin(), ctx->seen.end(), key) == ctx->seen.end()) {
     ctx->seen.push_back(std::move(key));
     if (ctx->seen.size() > SearchCtx::kSeen) ctx->seen.erase(ctx->seen.begin());
-    return launch_search(lib, ctx, P, path, variant, wsb, s, false, true);
+    return launch_search(lib, ctx, P, path, variant, wsb, s, lib->timing, false, true);
   }
   // a recent shape again: capture it (on any capture failure, launch eagerly)
   HIP_TRY(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
-  rc = launch_search(lib, ctx, P, path, variant, wsb, ctx->cap, true, true);
+  rc = launch_search(lib, ctx, P, path, variant, wsb, ctx->cap, lib->timing, true, true);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(ctx->cap, &g);
   hipGraphExec_t ex = nullptr;
@@ -677,7 +782,7 @@ static fps_status run_search(fps_library *lib, SearchCtx *ctx, Plan &P, fps_path
     (void)hipGetLastError();
     fps_clear_error();
     ctx->graph_failures++;
-    return launch_search(lib, ctx, P, path, variant, wsb, s, false, true);
+    return launch_search(lib, ctx, P, path, variant, wsb, s, lib->timing, false, true);
   }
   if (ctx->graphs.size() >= SearchCtx::kGraphs) {
     (void)hipGraphExecDestroy(ctx->graphs.front().second);
@@ -739,11 +844,12 @@ fps_status fps_search_impl(fps_library *lib, SearchCtx *ctx, const uint64_t *que
   HIP_TRY(hipStreamSynchronize(s));
   float ms = 0;
   for (uint32_t p = 0; p < ctx->last_phases; ++p)
-    if (hipEventElapsedTime(&ms, ctx->ev[2 + 2 * p], ctx->ev[3 + 2 * p]) == hipSuccess)
+    if ((ctx->last_timed >> p & 1u) &&
+        hipEventElapsedTime(&ms, ctx->ev[2 + 2 * p], ctx->ev[3 + 2 * p]) == hipSuccess)
       ctx->last.scan_ms += ms;
-  if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess) ctx->last.total_ms = ms;
-  ctx->last.scan_launches = ctx->last_phases *
-                            (path == FPS_PATH_SINGLE ? (uint32_t)(P.q) : 1u);
+  if (ctx->last_total_timed && hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess)
+    ctx->last.total_ms = ms;
+  ctx->last.scan_launches = ctx->last_launches;
   ctx->sum_scan_ms += ctx->last.scan_ms;
   ctx->sum_total_ms += ctx->last.total_ms;
   ctx->sum_calls += 1;
@@ -886,7 +992,7 @@ static fps_status resolve_path(fps_library *lib, SearchCtx *ctx, Plan &P, fps_pa
   fps_path bp = FPS_PATH_POPCOUNT;
   int bv = 0;
   for (const auto &cand : tune_candidates(P)) {
-    fps_status rc = launch_search(lib, ctx, P, cand.first, cand.second, wsb, s);
+    fps_status rc = launch_search(lib, ctx, P, cand.first, cand.second, wsb, s, true);
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(s));
     float ms = 0;

@@ -143,6 +143,38 @@ def test_graph_replay(small, path):
     assert np.array_equal(hits, ohits)
 
 
+@pytest.mark.parametrize("path", PATHS)
+def test_timing_modes(small, path):
+    """Device timing is opt-in: results are identical with and without it; with
+    it, every call reports positive scan and total device time, also from a
+    replayed graph; without it both are zero."""
+    lib_np, lib = small
+    qs = fpsynth.batch_queries(lib_np, 40, 800).words
+    k, masks = fpsynth.uneven_params(40, 800)
+    lib.set_path(path)
+    try:
+        for timing in (False, True, False, True):
+            lib.set_timing(timing)
+            for rep in range(3):  # eager, eager (seen), graph replay
+                say("case: timing", timing, "path", path, "rep", rep)
+                hits, off = lib.search_batch(qs, k, masks)
+                st = lib.last_stats()
+                ohits, ooff = oracle.search_batch(lib_np.words, qs, k, lib.strides, masks)
+                assert np.array_equal(off, ooff) and np.array_equal(hits, ohits)
+                assert st["scan_launches"] >= 1
+                if timing:
+                    assert st["scan_ms"] > 0 and st["total_ms"] >= st["scan_ms"], st
+                else:
+                    assert st["scan_ms"] == 0 and st["total_ms"] == 0, st
+            one = lib.search(qs[0], 30)
+            st = lib.last_stats()
+            assert np.array_equal(one, oracle.search(lib_np.words, qs[0], 30))
+            assert (st["scan_ms"] > 0) == timing and (st["total_ms"] > 0) == timing
+    finally:
+        lib.set_timing(False)
+        lib.set_path(fps.PATH_AUTO)
+
+
 def test_autotuner_and_cache(tmp_path, monkeypatch):
     """AUTO times every candidate on the first batch of a shape, caches the
     winner (also in the FPS_TUNE_CACHE file), and a new handle reuses it."""
@@ -225,6 +257,27 @@ def test_two_phase_bounds(small, path, sample, phase):
         check_batch(lib_np, lib, qs, k, masks, path, f"sample {sample} phase {phase}")
         got = lib.search(qs[0], 30)
         assert np.array_equal(got, oracle.search(lib_np.words, qs[0], 30))
+    finally:
+        lib.set_tuning()
+
+
+@pytest.mark.parametrize("sample,k,phases", [(4096, 30, 1), (512, 30, 1), (256, 30, 2),
+                                             (4096, 500, 2), (64, 1, 1), (64, 100, 2)])
+@pytest.mark.parametrize("path", PATHS)
+def test_phase_schedule(small, path, sample, k, phases):
+    """One scan phase when the first bound admits few records (k * n / sample
+    <= 8192), geometric phases otherwise; a batch of 8 and a single query, both
+    against the oracle."""
+    lib_np, lib = small
+    qs = fpsynth.batch_queries(lib_np, 8, 77 + k).words
+    lib.set_tuning(sample_records=sample)
+    try:
+        st = check_batch(lib_np, lib, qs, k, None, path, f"schedule s={sample} k={k}")
+        per_phase = 8 if path == fps.PATH_SINGLE else 1
+        assert st["scan_launches"] == phases * per_phase, st
+        got = lib.search(qs[0], k)
+        assert np.array_equal(got, oracle.search(lib_np.words, qs[0], k))
+        assert lib.last_stats()["scan_launches"] == phases
     finally:
         lib.set_tuning()
 
