@@ -44,6 +44,31 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# HBM traffic of the single-query scan kernel, from two rocprofv3 counter runs
+# (FETCH_SIZE, WRITE_SIZE) scaled by a calibration copy; valid only while the
+# kernel sources hash to what the summary records.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_scan_single.single_top30_95M.hbm_traffic.txt")
+TRAFFIC_SOURCES = ["paper_1906_06170_amd/csrc/kernels.hip", "paper_1906_06170_amd/csrc/cand.h",
+                   "paper_1906_06170_amd/csrc/fps_internal.h"]
+
+
+def measured_traffic():
+    import hashlib
+    try:
+        lines = open(TRAFFIC_PROFILE).read().splitlines()
+    except OSError:
+        return None
+    vals = dict(l.split(":", 1) for l in lines if l.startswith(("traffic_bytes_per_launch:",
+                                                                  "source_sha256:")))
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if vals.get("source_sha256", "").strip() != h.hexdigest():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,7 +164,8 @@ def main():
             "layout_gbs": layout, "layout_frac": layout / HBM_PEAK_GBS,
         }
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                           "traffic": measured_traffic(),
                            "kernel": "k_scan_single",
                            "bytes_per_launch": ALGO_BYTES_PER_RECORD * n / max(1, launches / K),
                            "launch_avg_ms": scan_ms / max(1, launches)}
