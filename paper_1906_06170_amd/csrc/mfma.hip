@@ -280,7 +280,7 @@ __global__ __launch_bounds__(256, WPE) void k_scan_mfma_i8(Lib lib, Workspace ws
     }
     // expand stage s + 1 into the other buffer
     if (s + 1 < nst) expand(R1, lds[(s + 1) & 1], tid);
-    __syncthreads();
+    lds_barrier();
     cur = nxt;
     nxt = nn;
     R1 = R2;

@@ -64,24 +64,23 @@ __device__ uint32_t pop_digits(uint32_t p) {
   return pat;
 }
 
-// Thread (record tid >> 1, half tid & 1) writes fragments 3h .. 3h + 2.
-__device__ __forceinline__ void expand_f4(const Regs &R, uint8_t *buf, const uint32_t *poptab,
-                                          uint32_t tid) {
-  const uint32_t rr = tid >> 1, h = tid & 1;
-  const uint64_t ra = R.ok ? R.a : 0, rb = R.ok ? R.b : 0;
-  const uint32_t rc = R.ok ? R.c : 0, rd = R.ok ? R.d : 0;
-  const uint32_t ch[3] = {h ? (uint32_t)(rb >> 32) : (uint32_t)ra, h ? rc : (uint32_t)(ra >> 32),
-                          h ? rd : (uint32_t)rb};
-  uint32_t dw[12];
+// Thread tid expands record tid of a 256-record stage: six 16-byte fragments
+// (keys of a lo, a hi, b lo, b hi, c, d) and the |r| digits in dword 3 of the
+// last one.
+__device__ __forceinline__ void expand_f4(const Rec1 &R, bool ok, uint8_t *buf,
+                                          const uint32_t *poptab, uint32_t tid) {
+  const uint64_t ra = ok ? R.a : 0, rb = ok ? R.b : 0;
+  const uint32_t rc = ok ? R.c : 0, rd = ok ? R.d : 0;
+  const uint32_t ch[6] = {(uint32_t)ra, (uint32_t)(ra >> 32), (uint32_t)rb,
+                          (uint32_t)(rb >> 32), rc, rd};
+  uint32_t dw[24];
 #pragma unroll
-  for (int f = 0; f < 3; ++f) spread_f4(ch[f], kDigitsRecord, dw + 4 * f);
-  if (h == 1) {
-    const uint32_t pr = (uint32_t)(__popcll(ra) + __popcll(rb) + __popc(rc) + __popc(rd));
-    dw[11] = poptab[R.ok ? pr : 255u];
-  }
-  v4i_ *dst = reinterpret_cast<v4i_ *>(buf + rr * kF4Stride + 48 * h);
+  for (int f = 0; f < 6; ++f) spread_f4(ch[f], kDigitsRecord, dw + 4 * f);
+  const uint32_t pr = (uint32_t)(__popcll(ra) + __popcll(rb) + __popc(rc) + __popc(rd));
+  dw[23] = poptab[ok ? pr : 255u];
+  v4i_ *dst = reinterpret_cast<v4i_ *>(buf + tid * kF4Stride);
 #pragma unroll
-  for (int f = 0; f < 3; ++f) {
+  for (int f = 0; f < 6; ++f) {
     v4i_ v = {(int)dw[4 * f], (int)dw[4 * f + 1], (int)dw[4 * f + 2], (int)dw[4 * f + 3]};
     dst[f] = v;
   }
@@ -202,21 +201,79 @@ __device__ __forceinline__ void decode_f4(const Workspace &ws, const QBlock &qb,
   }
 }
 
+// Stages of 256 records (8 per work item); each thread holds the raw words of
+// one record for RING stages ahead, in registers named statically (the stage
+// loop is unrolled by RING), so the loads of stage s + RING + 1 are issued at
+// stage s and first waited for at stage s + RING.
+constexpr int kSubF4 = 256;
+constexpr int kStagesF4 = kBatchTile / kSubF4;
+static_assert(kStagesF4 % 4 == 0, "the stage loop is unrolled by up to 4");
+
+// Multiplies one stage (LDS buffer buf, stage st) for this wave's queries and
+// decodes the hits.  COLS = false: every column block; COLS = true: the blocks
+// of this wave (wv, wv + 4).
+template <int MQ, bool COLS>
+__device__ __forceinline__ void stage_f4(const Workspace &ws, const QBlock &qb, const Stage &st,
+                                         const uint8_t *buf, uint32_t row0, uint32_t lane,
+                                         uint32_t wv, const v8i (&A)[MQ][3],
+                                         const v16f (&C)[MQ]) {
+  constexpr int kCols = kSubF4 / 32;
+  if (COLS) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int c = (int)wv + 4 * h;
+      if (st.g0 + 32 * c >= st.g1) break;
+      v8i B[3];
+      v16f acc[MQ];
+      load_b_f4<MQ>(buf, c, lane, B);
+      multiply_f4<MQ>(A, B, C, acc);
+      if (__ballot(or_bits<MQ>(acc) < 0) != 0) decode_f4<MQ>(ws, qb, st, c, row0, lane, acc);
+    }
+    return;
+  }
+  // First pass: every column block, the sign test folded into a per-lane mask
+  // of column blocks with a negative result.  Then only those blocks are
+  // multiplied again and decoded.
+  uint32_t hit_cols = 0;
+  v8i B0[3], B1[3];
+  load_b_f4<MQ>(buf, 0, lane, B0);
+#pragma unroll
+  for (int c = 0; c < kCols; c += 2) {
+    v16f acc[MQ];
+    load_b_f4<MQ>(buf, c + 1, lane, B1);
+    multiply_f4<MQ>(A, B0, C, acc);
+    hit_cols |= (or_bits<MQ>(acc) < 0 ? 1u : 0u) << c;
+    if (c + 2 < kCols) load_b_f4<MQ>(buf, c + 2, lane, B0);
+    multiply_f4<MQ>(A, B1, C, acc);
+    hit_cols |= (or_bits<MQ>(acc) < 0 ? 1u : 0u) << (c + 1);
+  }
+  if (__ballot(hit_cols != 0) != 0) {
+#pragma unroll 1
+    for (int c = 0; c < kCols; ++c) {
+      if (__ballot((hit_cols >> c) & 1u) == 0) continue;
+      v16f acc[MQ];
+      load_b_f4<MQ>(buf, c, lane, B0);
+      multiply_f4<MQ>(A, B0, C, acc);
+      decode_f4<MQ>(ws, qb, st, c, row0, lane, acc);
+    }
+  }
+}
+
 // COLS = false: the 4 waves hold different queries (128 * MQ per block).
-// COLS = true: the 4 waves share 32 * MQ queries and wave w multiplies column w.
-template <int MQ, int WPE, bool COLS>
+// COLS = true: the 4 waves share 32 * MQ queries and split the column blocks.
+template <int MQ, int WPE, bool COLS, int RING>
 __global__ __launch_bounds__(256, WPE) void k_scan_mfma_f4(Lib lib, Workspace ws, uint32_t nqb,
                                                            const uint64_t *item_off,
                                                            uint64_t tile_lo, uint64_t items,
                                                            uint64_t per_block) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[2][kSub * kF4Stride];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[2][kSubF4 * kF4Stride];
   __shared__ uint32_t poptab[256];
   const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const uint64_t it0 = (uint64_t)blockIdx.x * per_block;
   const uint64_t it1 = min(it0 + per_block, items);
   if (it0 >= it1) return;
   poptab[tid] = pop_digits(tid);
-  const uint64_t nst = (it1 - it0) * kSubPerTile;
+  const uint64_t nst = (it1 - it0) * kStagesF4;
   const uint32_t row0 = COLS ? 0u : wv * (MQ * 32);
   v8i A[MQ][3];
   v16f C[MQ];
@@ -224,70 +281,62 @@ __global__ __launch_bounds__(256, WPE) void k_scan_mfma_f4(Lib lib, Workspace ws
   QBlock qb{};
   bool wave_live = false;
 
-  Item pinfo = describe(ws, item_off, nqb, tile_lo, it0);
-  Item ninfo = pinfo;
-  Stage cur = stage_of(pinfo, 0);
-  Stage nxt = stage_of(pinfo, 1);
-  const Regs R0 = load_stage(lib, cur, tid);
-  Regs R1 = load_stage(lib, nxt, tid);
-  __syncthreads();  // poptab
-  expand_f4(R0, lds[0], poptab, tid);
-  __syncthreads();
-  for (uint64_t s = 0; s < nst; ++s) {
-    Stage nn = nxt;
-    Regs R2 = R1;
-    const uint64_t s2 = s + 2;
-    if (s2 < nst) {
-      const uint32_t sub = (uint32_t)(s2 % kSubPerTile);
-      if (sub == 0) pinfo = ninfo;
-      nn = stage_of(pinfo, sub);
-      R2 = load_stage(lib, nn, tid);
-      if (sub == kSubPerTile / 2 && it0 + s2 / kSubPerTile + 1 < it1)
-        ninfo = describe(ws, item_off, nqb, tile_lo, it0 + s2 / kSubPerTile + 1);
+  // loader: the next stage to load is tload, of work item litem
+  uint64_t tload = 0;
+  Item litem = describe(ws, item_off, nqb, tile_lo, it0);
+  // Past the last stage the loader yields empty stages (record 0 is read and
+  // expanded as invalid), so that every stage issues the same loads: the
+  // compiler can then count the loads in flight exactly and waits for each
+  // stage's records only when they are expanded.
+  auto next_stage = [&]() {
+    Stage st{litem.b, 0, 0};
+    if (tload < nst) {
+      const uint32_t sub = (uint32_t)(tload % kStagesF4);
+      if (sub == 0 && tload > 0)
+        litem = describe(ws, item_off, nqb, tile_lo, it0 + tload / kStagesF4);
+      st = stage_of<kSubF4>(litem, sub);
     }
-    if (cur.b != a_qb) {
-      a_qb = cur.b;
-      qb = ws.qblocks[cur.b];
-      wave_live = qb.count > row0;
-      build_a_f4<MQ>(ws, qb, row0, lane, A, C);
-    }
-    const uint8_t *buf = lds[s & 1];
-    if (COLS && wave_live && cur.g0 + 32 * wv < cur.g1) {
-      v8i B[3];
-      v16f acc[MQ];
-      load_b_f4<MQ>(buf, (int)wv, lane, B);
-      multiply_f4<MQ>(A, B, C, acc);
-      if (__ballot(or_bits<MQ>(acc) < 0) != 0) decode_f4<MQ>(ws, qb, cur, (int)wv, row0, lane, acc);
-    }
-    if (!COLS && wave_live && cur.g1 > cur.g0) {
-      int32_t any = 0;
-      v8i B0[3], B1[3];
-      load_b_f4<MQ>(buf, 0, lane, B0);
+    ++tload;
+    return st;
+  };
+  Stage cs = next_stage();
+  const Rec1 first = load_rec1(lib, cs, tid);
+  Stage S[RING];
+  Rec1 R[RING];
 #pragma unroll
-      for (int c = 0; c < kSub / 32; c += 2) {
-        v16f acc[MQ];
-        load_b_f4<MQ>(buf, c + 1, lane, B1);
-        multiply_f4<MQ>(A, B0, C, acc);
-        any |= or_bits<MQ>(acc);
-        if (c + 2 < kSub / 32) load_b_f4<MQ>(buf, c + 2, lane, B0);
-        multiply_f4<MQ>(A, B1, C, acc);
-        any |= or_bits<MQ>(acc);
-      }
-      if (__ballot(any < 0) != 0) {
-#pragma unroll 1
-        for (int c = 0; c < kSub / 32; ++c) {
-          v16f acc[MQ];
-          load_b_f4<MQ>(buf, c, lane, B0);
-          multiply_f4<MQ>(A, B0, C, acc);
-          if (__ballot(or_bits<MQ>(acc) < 0) != 0) decode_f4<MQ>(ws, qb, cur, c, row0, lane, acc);
+  for (int j = 1; j <= RING; ++j) {
+    S[j % RING] = next_stage();
+    R[j % RING] = load_rec1(lib, S[j % RING], tid);
+  }
+  __syncthreads();  // poptab
+  expand_f4(first, cs.g0 + tid < cs.g1, lds[0], poptab, tid);
+  __syncthreads();
+  // nst is a multiple of kStagesF4, hence of RING
+  for (uint64_t s0 = 0; s0 < nst; s0 += RING) {
+#pragma unroll
+    for (int j = 0; j < RING; ++j) {
+      {
+        if (cs.b != a_qb) {
+          a_qb = cs.b;
+          const cptr<QBlock> q = as_const(ws.qblocks) + cs.b;
+          qb.first = q->first;
+          qb.count = q->count;
+          qb.rset = q->rset;
+          qb.tiles = q->tiles;
+          wave_live = qb.count > row0;
+          build_a_f4<MQ>(ws, qb, row0, lane, A, C);
         }
+        if (wave_live && cs.g1 > cs.g0)
+          stage_f4<MQ, COLS>(ws, qb, cs, lds[j & 1], row0, lane, wv, A, C);
+        const int nx = (j + 1) % RING;  // a constant after unrolling
+        const Stage cn = S[nx];
+        expand_f4(R[nx], cn.g0 + tid < cn.g1, lds[(j + 1) & 1], poptab, tid);
+        S[nx] = next_stage();
+        R[nx] = load_rec1(lib, S[nx], tid);
+        lds_barrier();
+        cs = cn;
       }
     }
-    if (s + 1 < nst) expand_f4(R1, lds[(s + 1) & 1], poptab, tid);
-    __syncthreads();
-    cur = nxt;
-    nxt = nn;
-    R1 = R2;
   }
 }
 
@@ -317,14 +366,14 @@ void launch_scan_mfma_f4(const Lib &lib, const Workspace &ws, uint32_t nqb,
   const uint64_t per = (items + blocks - 1) / blocks;
   blocks = (items + per - 1) / per;
   const dim3 g((uint32_t)blocks), b(256);
-#define FPS_F4_LAUNCH(MQ, WPE, COLS)                                                       \
-  launch_k((k_scan_mfma_f4<MQ, WPE, COLS>), g, b, s, ev, lib, ws, nqb, item_off, tile_lo, items, \
-           per)
+#define FPS_F4_LAUNCH(MQ, WPE, COLS, RING)                                                 \
+  launch_k((k_scan_mfma_f4<MQ, WPE, COLS, RING>), g, b, s, ev, lib, ws, nqb, item_off, tile_lo, \
+           items, per)
   switch (variant) {
-    case 1: FPS_F4_LAUNCH(4, 1, false); break;
-    case 2: FPS_F4_LAUNCH(2, 2, true); break;
-    case 3: FPS_F4_LAUNCH(1, 2, false); break;
-    default: FPS_F4_LAUNCH(2, 2, false); break;
+    case 1: FPS_F4_LAUNCH(4, 1, false, 2); break;
+    case 2: FPS_F4_LAUNCH(2, 2, true, 4); break;
+    case 3: FPS_F4_LAUNCH(1, 2, false, 4); break;
+    default: FPS_F4_LAUNCH(2, 2, false, 4); break;
   }
 #undef FPS_F4_LAUNCH
 }

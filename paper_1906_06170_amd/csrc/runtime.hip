@@ -325,17 +325,20 @@ fps_status fps_make_rangeset(const fps_library *lib, uint32_t mask, RangeSet *rs
 // (b1 = G * S1, b2 = G * b1, ...), and after each phase the bound is refined to
 // the keff-th smallest distance of the prefix scanned so far.  A phase
 // [b_i, b_i+1) then appends about keff * (b_i+1 - b_i) / b_i records, times a
-// small factor for ties at the bound; G = 4096 / keff (clamped to 8..64) keeps
-// that near a few thousand per query.
+// small factor for ties at the bound.  G = A / keff clamped to 8..64, with
+// A = 4096 for batches of <= kSegQueries queries (appends are cheap there and a
+// phase costs a launch) and A = 512 for larger batches, whose matrix-core
+// scans pay for every append with a decode of the result tile.
 static std::vector<uint64_t> phase_bounds(const fps_library *lib, uint64_t max_neff,
-                                          uint64_t max_keff, uint64_t s1) {
+                                          uint64_t max_keff, uint64_t s1, uint32_t q) {
   std::vector<uint64_t> b{0};
   s1 = std::max<uint64_t>(s1, 1);
   if (!lib->phase_a && (double)max_keff * (double)max_neff <= (double)kSinglePhaseAppends * s1) {
     b.push_back(UINT64_MAX);
     return b;
   }
-  const uint64_t G = std::min<uint64_t>(64, std::max<uint64_t>(8, 4096 / std::max<uint64_t>(max_keff, 1)));
+  const uint64_t A = q <= kSegQueries ? 4096 : 512;
+  const uint64_t G = std::min<uint64_t>(64, std::max<uint64_t>(8, A / std::max<uint64_t>(max_keff, 1)));
   uint64_t a = lib->phase_a ? lib->phase_a : s1 * G;
   while (a < max_neff && b.size() < (size_t)kMaxPhases) {
     b.push_back(a);
@@ -399,7 +402,7 @@ fps_status fps_plan(const fps_library *lib, uint32_t q, const uint32_t *k, const
     max_keff = std::max(max_keff, keff);
   }
   const uint64_t s1 = lib->sample;
-  P->bounds = phase_bounds(lib, max_neff, max_keff, s1);
+  P->bounds = phase_bounds(lib, max_neff, max_keff, s1, q);
   for (uint32_t i = 0; i < q; ++i) {
     const RangeSet &rs = P->rsets[rs_of[i]];
     QueryInfo &qi = P->qinfo[i];
