@@ -31,14 +31,17 @@ struct Resv {
   uint32_t sbase;  // first position in the spill area (for the part past segcap)
 };
 
-__device__ __forceinline__ uint32_t *seg_counter(const Workspace &ws, const QueryInfo *qi,
-                                                 uint32_t s) {
+// The candidate-buffer fields of a query: QueryInfo, or a copy of those fields
+// (any type with cand_off, ctr_off, nseg, segcap, spillcap).
+template <class QI>
+__device__ __forceinline__ uint32_t *seg_counter(const Workspace &ws, const QI *qi, uint32_t s) {
   return ws.ctr + qi->ctr_off + s * kCtrStride;
 }
 
 // Reserves n slots in segment seg (one lane calls this for its group).
-__device__ __forceinline__ Resv cand_reserve(const Workspace &ws, const QueryInfo *qi,
-                                             uint32_t seg, uint32_t n) {
+template <class QI>
+__device__ __forceinline__ Resv cand_reserve(const Workspace &ws, const QI *qi, uint32_t seg,
+                                             uint32_t n) {
   Resv r;
   r.base = atomicAdd(seg_counter(ws, qi, seg), n);
   r.sbase = 0;
@@ -51,7 +54,8 @@ __device__ __forceinline__ Resv cand_reserve(const Workspace &ws, const QueryInf
 }
 
 // Stores the p-th key of a reservation.
-__device__ __forceinline__ void cand_put(const Workspace &ws, const QueryInfo *qi, uint32_t seg,
+template <class QI>
+__device__ __forceinline__ void cand_put(const Workspace &ws, const QI *qi, uint32_t seg,
                                          const Resv &r, uint32_t p, uint64_t key) {
   const uint32_t segcap = qi->segcap;
   const uint32_t pos = r.base + p;

@@ -86,6 +86,111 @@ __device__ __forceinline__ Rec1 load_rec1(const Lib &lib, const Stage &st, uint3
   return R;
 }
 
+// ---------------------------------------------------------------------------
+// Hits of the matrix-core kernels, gathered per wave in LDS and written out in
+// batches.  Decoding a result tile then touches LDS only; a flush (list nearly
+// full, a new query block, the end of the kernel) reserves each row's hits
+// with one device atomic -- one per row, all in flight together -- and stores
+// the keys.  Global loads and returning atomics wait on the same counter as
+// the record loads in flight, so doing them per tile would stall the record
+// prefetch at every hit.
+// ---------------------------------------------------------------------------
+struct RowInfo {  // a query row's candidate-buffer fields (see QueryInfo)
+  uint64_t cand_off;
+  uint32_t ctr_off, nseg, segcap, spillcap;
+  uint32_t T1;  // T + 1: the distance of a pair is its product u plus T1
+  uint32_t pad;
+};
+
+constexpr uint32_t kHitCap = 256;  // list entries per wave
+
+// Zeroes the per-row counts of a wave (before its first flush).
+template <int ROWS>
+__device__ __forceinline__ void hits_init(uint32_t lane, uint32_t *cnt) {
+  for (uint32_t lr = lane; lr < (uint32_t)ROWS; lr += 64) cnt[lr] = 0;
+}
+
+struct HitBuf {
+  RowInfo *row;    // the wave's rows
+  uint32_t *cnt;   // per row: hits since the last flush
+  uint32_t *base;  // per row: reservation of the flush
+  uint32_t *sbase;
+  uint64_t *list;  // (row << 49) | (d << 41) | (rank << 32) | record index
+  uint32_t n;      // entries (wave-uniform)
+};
+
+// Loads the RowInfo of rows row0 .. row0 + ROWS - 1 of query block qb.
+template <int ROWS>
+__device__ __forceinline__ void hits_rows(const Workspace &ws, const QBlock &qb, uint32_t row0,
+                                          uint32_t lane, HitBuf &hb) {
+#pragma unroll
+  for (int k = 0; k < (ROWS + 63) / 64; ++k) {
+    const uint32_t lr = lane + 64u * k;
+    if (lr < (uint32_t)ROWS) {
+      RowInfo ri{0, 0, 1, 0, 0, 0, 0};
+      const uint32_t row = row0 + lr;
+      if (row < qb.count) {
+        const uint32_t q = ws.perm[qb.first + row];
+        const QueryInfo *qi = ws.qinfo + q;
+        ri.cand_off = qi->cand_off;
+        ri.ctr_off = qi->ctr_off;
+        ri.nseg = qi->nseg;
+        ri.segcap = qi->segcap;
+        ri.spillcap = qi->spillcap;
+        ri.T1 = ws.T[q] + 1u;
+      }
+      hb.row[lr] = ri;
+      hb.cnt[lr] = 0;
+    }
+  }
+}
+
+// Rows with a nonzero count have their RowInfo loaded (a hit needs a row of
+// the current query block), so an empty list reads no RowInfo at all.
+template <int ROWS>
+__device__ __forceinline__ void hits_flush(const Workspace &ws, uint32_t lane, HitBuf &hb) {
+  if (hb.n == 0) return;
+#pragma unroll
+  for (int k = 0; k < (ROWS + 63) / 64; ++k) {
+    const uint32_t lr = lane + 64u * k;
+    if (lr < (uint32_t)ROWS) {
+      const uint32_t c = hb.cnt[lr];
+      if (c) {
+        const RowInfo *ri = hb.row + lr;
+        const Resv rv = cand_reserve(ws, ri, blockIdx.x % ri->nseg, c);
+        hb.base[lr] = rv.base;
+        hb.sbase[lr] = rv.sbase;
+        hb.cnt[lr] = 0;
+      }
+    }
+  }
+  for (uint32_t i = lane; i < hb.n; i += 64) {
+    const uint64_t e = hb.list[i];
+    const uint32_t lr = (uint32_t)(e >> 49), d = (uint32_t)(e >> 41) & 0xFFu;
+    const uint32_t rank = (uint32_t)(e >> 32) & 0x1FFu;
+    const RowInfo *ri = hb.row + lr;
+    const Resv rv{hb.base[lr], hb.sbase[lr]};
+    cand_put(ws, ri, blockIdx.x % ri->nseg, rv, rank, ((uint64_t)d << 32) | (uint32_t)e);
+  }
+  hb.n = 0;
+}
+
+// Adds the lanes with hit set (local row lr, product u, record g) to the list.
+template <int ROWS>
+__device__ __forceinline__ void hits_add(const Workspace &ws, uint32_t lane, HitBuf &hb, bool hit,
+                                         uint32_t lr, int32_t u, uint64_t g) {
+  const uint64_t bal = __ballot(hit);
+  if (bal == 0) return;
+  if (hb.n + 64 > kHitCap) hits_flush<ROWS>(ws, lane, hb);
+  if (hit) {
+    const uint32_t rank = atomicAdd(hb.cnt + lr, 1u);
+    const uint32_t d = (uint32_t)(u + (int32_t)hb.row[lr].T1);
+    hb.list[hb.n + rank_below(bal)] = ((uint64_t)lr << 49) | ((uint64_t)d << 41) |
+                                      ((uint64_t)rank << 32) | (uint32_t)g;
+  }
+  hb.n += (uint32_t)__popcll(bal);
+}
+
 // Block barrier for LDS traffic: this wave's LDS operations complete, then the
 // barrier.  __syncthreads() would also wait for every outstanding global load
 // (the workgroup fence waits on the one counter that loads and stores share),

@@ -164,39 +164,23 @@ __device__ __forceinline__ int32_t or_bits(const v16f (&acc)[MQ]) {
   return any;
 }
 
-// Appends the hits of one 32x32 result tile (column block c of stage st); the
-// 32 lanes of a half-wave share one query row per element: one atomic each.
+// Adds the hits of one 32x32 result tile (column block c of stage st) to the
+// wave's hit list.  Lane layout of the result: column lane & 31, rows
+// 8 (e >> 2) + 4 (lane >> 5) + (e & 3) of element e.
 template <int MQ>
 __device__ __forceinline__ void decode_f4(const Workspace &ws, const QBlock &qb, const Stage &st,
                                           int c, uint32_t row0, uint32_t lane,
-                                          const v16f (&acc)[MQ]) {
+                                          const v16f (&acc)[MQ], HitBuf &hb) {
   const uint64_t g = st.g0 + 32 * c + (lane & 31);
   const uint32_t half = lane >> 5;
-  const uint32_t below = (uint32_t)((1ull << (lane & 31)) - 1ull);
 #pragma unroll
   for (int mq = 0; mq < MQ; ++mq) {
 #pragma unroll 1
     for (int e = 0; e < 16; ++e) {
       const float u = acc[mq][e];
-      const uint32_t row = row0 + mq * 32 + 8 * (e >> 2) + 4 * half + (e & 3);
-      const bool hit = u < 0.0f && row < qb.count && g < st.g1;
-      const uint64_t bal = __ballot(hit);
-      if (bal == 0) continue;
-      const uint32_t mine = (uint32_t)(bal >> (32 * half));
-      Resv rv{0, 0};
-      uint32_t q = 0;
-      if (mine) q = ws.perm[qb.first + row];
-      const QueryInfo *qi = ws.qinfo + q;
-      const uint32_t seg = blockIdx.x % (mine ? qi->nseg : 1u);
-      if (mine && (lane & 31) == (uint32_t)(__ffs(mine) - 1))
-        rv = cand_reserve(ws, qi, seg, (uint32_t)__popc(mine));
-      const uint32_t lead = mine ? 32 * half + (uint32_t)(__ffs(mine) - 1) : lane;
-      rv.base = __shfl(rv.base, (int)lead);
-      rv.sbase = __shfl(rv.sbase, (int)lead);
-      if (hit) {
-        const uint32_t d = (uint32_t)((int32_t)u + (int32_t)ws.T[q] + 1);
-        cand_put(ws, qi, seg, rv, (uint32_t)__popc(mine & below), ((uint64_t)d << 32) | g);
-      }
+      const uint32_t lr = mq * 32 + 8 * (e >> 2) + 4 * half + (e & 3);
+      const bool hit = u < 0.0f && row0 + lr < qb.count && g < st.g1;
+      hits_add<MQ * 32>(ws, lane, hb, hit, lr, (int32_t)u, g);
     }
   }
 }
@@ -216,7 +200,7 @@ template <int MQ, bool COLS>
 __device__ __forceinline__ void stage_f4(const Workspace &ws, const QBlock &qb, const Stage &st,
                                          const uint8_t *buf, uint32_t row0, uint32_t lane,
                                          uint32_t wv, const v8i (&A)[MQ][3],
-                                         const v16f (&C)[MQ]) {
+                                         const v16f (&C)[MQ], HitBuf &hb) {
   constexpr int kCols = kSubF4 / 32;
   if (COLS) {
 #pragma unroll
@@ -227,7 +211,7 @@ __device__ __forceinline__ void stage_f4(const Workspace &ws, const QBlock &qb, 
       v16f acc[MQ];
       load_b_f4<MQ>(buf, c, lane, B);
       multiply_f4<MQ>(A, B, C, acc);
-      if (__ballot(or_bits<MQ>(acc) < 0) != 0) decode_f4<MQ>(ws, qb, st, c, row0, lane, acc);
+      if (__ballot(or_bits<MQ>(acc) < 0) != 0) decode_f4<MQ>(ws, qb, st, c, row0, lane, acc, hb);
     }
     return;
   }
@@ -254,7 +238,7 @@ __device__ __forceinline__ void stage_f4(const Workspace &ws, const QBlock &qb, 
       v16f acc[MQ];
       load_b_f4<MQ>(buf, c, lane, B0);
       multiply_f4<MQ>(A, B0, C, acc);
-      decode_f4<MQ>(ws, qb, st, c, row0, lane, acc);
+      decode_f4<MQ>(ws, qb, st, c, row0, lane, acc, hb);
     }
   }
 }
@@ -266,12 +250,18 @@ __global__ __launch_bounds__(256, WPE) void k_scan_mfma_f4(Lib lib, Workspace ws
                                                            const uint64_t *item_off,
                                                            uint64_t tile_lo, uint64_t items,
                                                            uint64_t per_block) {
+  constexpr int kRows = MQ * 32;  // query rows of a wave
   __shared__ __attribute__((aligned(16))) uint8_t lds[2][kSubF4 * kF4Stride];
   __shared__ uint32_t poptab[256];
+  __shared__ RowInfo h_row[4][kRows];
+  __shared__ uint32_t h_cnt[4][kRows], h_base[4][kRows], h_sbase[4][kRows];
+  __shared__ uint64_t h_list[4][kHitCap];
   const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const uint64_t it0 = (uint64_t)blockIdx.x * per_block;
   const uint64_t it1 = min(it0 + per_block, items);
   if (it0 >= it1) return;
+  HitBuf hb{h_row[wv], h_cnt[wv], h_base[wv], h_sbase[wv], h_list[wv], 0};
+  hits_init<kRows>(lane, h_cnt[wv]);
   poptab[tid] = pop_digits(tid);
   const uint64_t nst = (it1 - it0) * kStagesF4;
   const uint32_t row0 = COLS ? 0u : wv * (MQ * 32);
@@ -317,6 +307,7 @@ __global__ __launch_bounds__(256, WPE) void k_scan_mfma_f4(Lib lib, Workspace ws
     for (int j = 0; j < RING; ++j) {
       {
         if (cs.b != a_qb) {
+          hits_flush<kRows>(ws, lane, hb);  // the rows change with the query block
           a_qb = cs.b;
           const cptr<QBlock> q = as_const(ws.qblocks) + cs.b;
           qb.first = q->first;
@@ -325,9 +316,10 @@ __global__ __launch_bounds__(256, WPE) void k_scan_mfma_f4(Lib lib, Workspace ws
           qb.tiles = q->tiles;
           wave_live = qb.count > row0;
           build_a_f4<MQ>(ws, qb, row0, lane, A, C);
+          hits_rows<kRows>(ws, qb, row0, lane, hb);
         }
         if (wave_live && cs.g1 > cs.g0)
-          stage_f4<MQ, COLS>(ws, qb, cs, lds[j & 1], row0, lane, wv, A, C);
+          stage_f4<MQ, COLS>(ws, qb, cs, lds[j & 1], row0, lane, wv, A, C, hb);
         const int nx = (j + 1) % RING;  // a constant after unrolling
         const Stage cn = S[nx];
         expand_f4(R[nx], cn.g0 + tid < cn.g1, lds[(j + 1) & 1], poptab, tid);
@@ -338,6 +330,7 @@ __global__ __launch_bounds__(256, WPE) void k_scan_mfma_f4(Lib lib, Workspace ws
       }
     }
   }
+  hits_flush<kRows>(ws, lane, hb);
 }
 
 // Tile-shape variants of the fp4 kernel.
