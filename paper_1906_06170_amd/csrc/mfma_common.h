@@ -175,19 +175,27 @@ __device__ __forceinline__ void hits_flush(const Workspace &ws, uint32_t lane, H
   hb.n = 0;
 }
 
-// Adds the lanes with hit set (local row lr, product u, record g) to the list.
+// Adds the lanes with hit set to the list: local row lr (the same for the 32
+// lanes of a half-wave, as in a matrix-core result tile), product u, record g.
+// Ranks within a row come from the half-wave's ballot; the row's count is
+// updated by the half-wave's first lane (the wave owns its counts).
 template <int ROWS>
 __device__ __forceinline__ void hits_add(const Workspace &ws, uint32_t lane, HitBuf &hb, bool hit,
                                          uint32_t lr, int32_t u, uint64_t g) {
   const uint64_t bal = __ballot(hit);
   if (bal == 0) return;
   if (hb.n + 64 > kHitCap) hits_flush<ROWS>(ws, lane, hb);
+  const uint32_t half = lane >> 5;
+  const uint32_t mine = (uint32_t)(bal >> (32 * half));
+  const uint32_t below = (uint32_t)((1ull << (lane & 31)) - 1ull);
+  const uint32_t c0 = hb.cnt[lr];
   if (hit) {
-    const uint32_t rank = atomicAdd(hb.cnt + lr, 1u);
+    const uint32_t rank = c0 + (uint32_t)__popc(mine & below);
     const uint32_t d = (uint32_t)(u + (int32_t)hb.row[lr].T1);
     hb.list[hb.n + rank_below(bal)] = ((uint64_t)lr << 49) | ((uint64_t)d << 41) |
                                       ((uint64_t)rank << 32) | (uint32_t)g;
   }
+  if (mine != 0 && (lane & 31) == 0) hb.cnt[lr] = c0 + (uint32_t)__popc(mine);
   hb.n += (uint32_t)__popcll(bal);
 }
 

@@ -166,22 +166,44 @@ __device__ __forceinline__ int32_t or_bits(const v16f (&acc)[MQ]) {
 
 // Adds the hits of one 32x32 result tile (column block c of stage st) to the
 // wave's hit list.  Lane layout of the result: column lane & 31, rows
-// 8 (e >> 2) + 4 (lane >> 5) + (e & 3) of element e.
+// 8 (e >> 2) + 4 (lane >> 5) + (e & 3) of element e.  A per-lane mask of the
+// negative elements, ORed over the wave, leaves only the elements with a hit
+// to visit.
 template <int MQ>
 __device__ __forceinline__ void decode_f4(const Workspace &ws, const QBlock &qb, const Stage &st,
                                           int c, uint32_t row0, uint32_t lane,
                                           const v16f (&acc)[MQ], HitBuf &hb) {
+  static_assert(MQ * 16 <= 64, "one bit per result element");
   const uint64_t g = st.g0 + 32 * c + (lane & 31);
   const uint32_t half = lane >> 5;
+  const bool col_ok = g < st.g1;
+  uint64_t m = 0;
 #pragma unroll
-  for (int mq = 0; mq < MQ; ++mq) {
-#pragma unroll 1
+  for (int mq = 0; mq < MQ; ++mq)
+#pragma unroll
     for (int e = 0; e < 16; ++e) {
-      const float u = acc[mq][e];
-      const uint32_t lr = mq * 32 + 8 * (e >> 2) + 4 * half + (e & 3);
-      const bool hit = u < 0.0f && row0 + lr < qb.count && g < st.g1;
-      hits_add<MQ * 32>(ws, lane, hb, hit, lr, (int32_t)u, g);
+      const float x = acc[mq][e];
+      m |= (uint64_t)(x < 0.0f ? 1u : 0u) << (16 * mq + e);
     }
+  if (!col_ok) m = 0;
+  uint64_t any = m;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) any |= __shfl_xor(any, o);
+  any = __builtin_amdgcn_readfirstlane((uint32_t)any) |
+        ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(any >> 32)) << 32);
+  while (any) {
+    const int b = __builtin_ctzll(any);
+    any &= any - 1;
+    const int mq = b >> 4, e = b & 15;
+    const uint32_t lr = mq * 32 + 8 * (e >> 2) + 4 * half + (e & 3);
+    const bool hit = ((m >> b) & 1u) != 0 && row0 + lr < qb.count;
+    float u = 0.0f;  // acc[mq][e], selected with constant indices only
+#pragma unroll
+    for (int k = 0; k < MQ; ++k)
+#pragma unroll
+      for (int f = 0; f < 16; ++f)
+        if (k == mq && f == e) u = acc[k][f];
+    hits_add<MQ * 32>(ws, lane, hb, hit, lr, (int32_t)u, g);
   }
 }
 

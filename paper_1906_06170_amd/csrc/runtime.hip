@@ -327,7 +327,7 @@ fps_status fps_make_rangeset(const fps_library *lib, uint32_t mask, RangeSet *rs
 // [b_i, b_i+1) then appends about keff * (b_i+1 - b_i) / b_i records, times a
 // small factor for ties at the bound.  G = A / keff clamped to 8..64, with
 // A = 4096 for batches of <= kSegQueries queries (appends are cheap there and a
-// phase costs a launch) and A = 512 for larger batches, whose matrix-core
+// phase costs a launch) and A = 256 for larger batches, whose matrix-core
 // scans pay for every append with a decode of the result tile.
 static std::vector<uint64_t> phase_bounds(const fps_library *lib, uint64_t max_neff,
                                           uint64_t max_keff, uint64_t s1, uint32_t q) {
@@ -337,7 +337,7 @@ static std::vector<uint64_t> phase_bounds(const fps_library *lib, uint64_t max_n
     b.push_back(UINT64_MAX);
     return b;
   }
-  const uint64_t A = q <= kSegQueries ? 4096 : 512;
+  const uint64_t A = q <= kSegQueries ? 4096 : 256;
   const uint64_t G = std::min<uint64_t>(64, std::max<uint64_t>(8, A / std::max<uint64_t>(max_keff, 1)));
   uint64_t a = lib->phase_a ? lib->phase_a : s1 * G;
   while (a < max_neff && b.size() < (size_t)kMaxPhases) {
