@@ -240,18 +240,25 @@ __device__ __forceinline__ void stage_f4(const Workspace &ws, const QBlock &qb, 
   // First pass: every column block, the sign test folded into a per-lane mask
   // of column blocks with a negative result.  Then only those blocks are
   // multiplied again and decoded.
+  // Software-pipelined: the products of column block c + 1 are issued before
+  // the sign test of block c, so the test and the next fragment reads overlap
+  // matrix-core work.
   uint32_t hit_cols = 0;
   v8i B0[3], B1[3];
+  v16f acc0[MQ], acc1[MQ];
   load_b_f4<MQ>(buf, 0, lane, B0);
+  multiply_f4<MQ>(A, B0, C, acc0);
+  load_b_f4<MQ>(buf, 1, lane, B1);
 #pragma unroll
   for (int c = 0; c < kCols; c += 2) {
-    v16f acc[MQ];
-    load_b_f4<MQ>(buf, c + 1, lane, B1);
-    multiply_f4<MQ>(A, B0, C, acc);
-    hit_cols |= (or_bits<MQ>(acc) < 0 ? 1u : 0u) << c;
+    multiply_f4<MQ>(A, B1, C, acc1);  // block c + 1
     if (c + 2 < kCols) load_b_f4<MQ>(buf, c + 2, lane, B0);
-    multiply_f4<MQ>(A, B1, C, acc);
-    hit_cols |= (or_bits<MQ>(acc) < 0 ? 1u : 0u) << (c + 1);
+    hit_cols |= (or_bits<MQ>(acc0) < 0 ? 1u : 0u) << c;
+    if (c + 2 < kCols) {
+      multiply_f4<MQ>(A, B0, C, acc0);  // block c + 2
+      load_b_f4<MQ>(buf, c + 3, lane, B1);
+    }
+    hit_cols |= (or_bits<MQ>(acc1) < 0 ? 1u : 0u) << (c + 1);
   }
   if (__ballot(hit_cols != 0) != 0) {
 #pragma unroll 1
