@@ -136,11 +136,15 @@ fps_status fps_set_graphs(fps_library *lib, int enable);
  * candidates regardless.  Errors: FPS_E_ARG. */
 fps_status fps_set_timing(fps_library *lib, int enable);
 
-/* Selects the tile shape of the matrix-core kernel: 0 = 64 queries per wave,
- * 1 = 64 per wave with two waves per SIMD, 2 = 128 per wave, 3 = 32 per wave
- * with two waves per SIMD, 4 = 64 queries shared by a block's four waves,
- * which split the records; -1 (default) lets the autotuner choose.  Results
- * never depend on it.  Errors: FPS_E_ARG. */
+/* Selects the tile shape of the matrix-core kernel of a path forced with
+ * fps_set_path.  int8: 0 = 64 queries per wave, 1 = 64 per wave with two waves
+ * per SIMD, 2 = 128 per wave, 3 = 32 per wave with two waves per SIMD, 4 = 64
+ * queries shared by a block's four waves, which split the records.  fp4: 0 = 64
+ * queries per wave with two waves per SIMD, 1 = 128 per wave, 2 = 64 queries
+ * shared by the four waves, 3 = 32 per wave with two waves per SIMD.  A value
+ * beyond the path's shapes wraps around.  -1 (default): the autotuner chooses
+ * under FPS_PATH_AUTO; a forced path takes int8 shape 1 or fp4 shape 0.
+ * Results never depend on it.  Errors: FPS_E_ARG (variant < -1 or >= 5). */
 fps_status fps_set_variant(fps_library *lib, int variant);
 
 /* ------------------------------------------------------------------------ */

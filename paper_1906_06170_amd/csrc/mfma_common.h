@@ -1,17 +1,20 @@
 // Work-item and stage bookkeeping shared by the matrix-core kernels.
 //
 // A block of a matrix-core kernel walks a contiguous run of work items (one
-// query block x one batch tile of kBatchTile records) as a stream of stages of
-// kSub records; the records of a stage are held in registers (one record per
-// two threads) before they are expanded into LDS.
+// query block x one batch tile of kBatchTile records) as a stream of stages;
+// the records of a stage are held in registers before they are expanded into
+// LDS.  The int8 kernel uses stages of kSub records (one record per two
+// threads, Regs); the fp4 kernel stages of 256 (one record per thread, Rec1).
+// Also here: the scalar-load view of the parameter tables, the LDS hit lists
+// and the LDS-only barrier.
 #pragma once
 #include "cand.h"
 #include "fps_internal.h"
 
 namespace fps {
 
-constexpr int kSub = 128;                       // records per LDS stage
-constexpr int kSubPerTile = kBatchTile / kSub;  // stages per work item
+constexpr int kSub = 128;                       // records per LDS stage (int8 kernel)
+constexpr int kSubPerTile = kBatchTile / kSub;  // stages per work item (int8 kernel)
 
 // A work item: query block b and the records [t0, t1) of one batch tile.
 struct Item {
