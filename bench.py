@@ -12,7 +12,8 @@ Also measured in the same run (secondary objects of the JSON line):
   uneven  : 4096 queries, k uniform over {1,10,30,100,1000}, masks over
             {A, A+B, A+B+C} of strides 40M / 35M / 20.4M
   serving : Poisson request arrivals, 1-64 queries per request, k in
-            {30,100,1000}, 10 ms deadline; p50 / p99 latency and throughput
+            {30,100,1000}, 10 ms deadline; p50 / p99 latency and throughput over
+            the arrivals after a 1 s warm-up (6 s per rate)
   cpu_baseline : the CPU oracle on the host's cores, on a bounded sample.
 
 Inputs are synthetic (fpsynth): the PubChem library of the paper is not
@@ -76,9 +77,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=95_417_114)
     ap.add_argument("--only", default="all",
-                    help="comma list of: single,batch,uneven,serve,cpu")
+                    help="comma list of: single,shard,batch,uneven,serve,cpu")
     ap.add_argument("--batch-steps", type=int, default=5)
-    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-seconds", type=float, default=6.0)
+    ap.add_argument("--serve-warmup", type=float, default=1.0,
+                    help="seconds of arrivals per rate excluded from the statistics")
     ap.add_argument("--serve-rates", default="200,1000,5000")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -94,7 +97,7 @@ def main():
               "the engine has no multi-GPU path in this build", file=sys.stderr)
         sys.exit(2)
     legs = set(args.only.split(",")) if args.only != "all" else {
-        "single", "batch", "uneven", "serve", "cpu"}
+        "single", "shard", "batch", "uneven", "serve", "cpu"}
 
     import torch
     import fpsynth
@@ -130,12 +133,16 @@ def main():
             lib.search(qs[i], 30)
         torch.cuda.synchronize()
         # the timed steps run untimed on the device (no HIP events) ...
+        per_q = []
         t = time.perf_counter()
         for i in range(W, W + K):
-            lib.search(qs[i], 30)
+            tq = time.perf_counter()
+            lib.search(qs[i], 30)  # synchronous: returns with the hits on the host
+            per_q.append(time.perf_counter() - tq)
         torch.cuda.synchronize()
         el = time.perf_counter() - t
         ms = el * 1000 / K
+        per_q = np.array(per_q) * 1000
         # ... then the same queries again with HIP events around every kernel
         # phase: the scan kernel's duration for the roofline
         lib.set_timing(True)
@@ -155,6 +162,8 @@ def main():
         layout = LAYOUT_BYTES_PER_RECORD * n / (per_query_scan * 1e-3) / 1e9
         single = {
             "ms_per_query": ms, "qps": 1000.0 / ms,
+            "ms_per_query_median": float(np.median(per_q)), "ms_per_query_min": float(per_q.min()),
+            "ms_per_query_max": float(per_q.max()),
             "gcmp_s": n / (ms * 1e-3) / 1e9,
             "scan_ms_per_query": per_query_scan,
             "scan_launches_per_query": launches / K,
@@ -170,6 +179,34 @@ def main():
                            "bytes_per_launch": ALGO_BYTES_PER_RECORD * n / max(1, launches / K),
                            "launch_avg_ms": scan_ms / max(1, launches)}
         log("single:", json.dumps(single))
+
+    # ---------------- one GPU's shard of an 8-GPU library ----------------
+    # The library cut into 8 equal strides; a query restricted to one of them
+    # is the per-GPU share of a library-sharded search (global indices; the
+    # eight top-k lists merge by (distance, index)).
+    if "shard" in legs:
+        G = 8
+        cuts = [n * s // G for s in range(G + 1)]
+        lib8 = fps.Library(lib_np.words, strides=cuts)
+        for i in range(W):
+            lib8.search(qs[i], 30, mask=1)
+        t = time.perf_counter()
+        for i in range(W, W + K):
+            lib8.search(qs[i], 30, mask=1)
+        sh_ms = (time.perf_counter() - t) * 1000 / K
+        lib8.set_timing(True)
+        s0 = lib8.last_stats()
+        for i in range(W, W + K):
+            lib8.search(qs[i], 30, mask=1)
+        s1 = lib8.last_stats()
+        sh_scan = (s1["scan_ms_sum"] - s0["scan_ms_sum"]) / K
+        nsh = cuts[1] - cuts[0]
+        out["shard"] = {"shards": G, "shard_records": nsh, "ms_per_query": sh_ms,
+                        "gcmp_s": nsh / (sh_ms * 1e-3) / 1e9, "scan_ms_per_query": sh_scan,
+                        "scan_hbm_frac": ALGO_BYTES_PER_RECORD * nsh / (sh_scan * 1e-3) / 1e9
+                        / HBM_PEAK_GBS}
+        lib8.close()
+        log("shard:", json.dumps(out["shard"]))
 
     # ---------------- batch of 1024 ----------------
     path = {"auto": fps.PATH_AUTO, "popcount": fps.PATH_POPCOUNT,
@@ -296,14 +333,18 @@ def serve(lib, lib_np, args, fps, fpsynth):
         th = threading.Thread(target=waiter)
         th.start()
         t0 = time.perf_counter()
+        t_meas = None
         for i in range(nreq):
             delay = arr[i] - (time.perf_counter() - t0)
             if delay > 0:
                 time.sleep(delay)
+            if t_meas is None and arr[i] >= args.serve_warmup:
+                srv.stats(reset=True)  # statistics cover arrivals after the warm-up
+                t_meas = time.perf_counter()
             tickets[i] = srv.submit(allq[offs[i]:offs[i + 1]], int(ks[i]), fps.MASK_ALL,
                                     deadline_us=10_000)
         done.wait()
-        el = time.perf_counter() - t0
+        el = time.perf_counter() - (t_meas if t_meas is not None else t0)
         th.join()
         st = srv.stats()
         srv.close()
@@ -333,10 +374,26 @@ def cpu_baseline(lib_np, qs, args):
         if time.perf_counter() - t > args.cpu_seconds or done >= 8:
             break
     el = time.perf_counter() - t
+    # the plain serial form on one core, over the first eighth of the library
+    n1 = max(1, n // 8)
+    t1 = time.perf_counter()
+    oracle.search(lib_np.words[:n1], qs[0], 30, nthreads=1)
+    el1 = time.perf_counter() - t1
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     r = {"value": done * n / el / 1e9, "unit": "G fp-compares/s", "cores": nth,
          "kind": "oracle",
          "sample": f"{done} full-library single queries (top-30 over {n} records), "
-                   f"threaded chunk-and-merge form, {el:.1f}s wall"}
+                   f"threaded chunk-and-merge form, {el:.1f}s wall",
+         "one_core": {"value": n1 / el1 / 1e9, "sample": f"one query over {n1} records, "
+                                                         f"serial form, {el1:.1f}s"},
+         "cpu_model": model, "host_cpus": os.cpu_count()}
     log("cpu:", json.dumps(r))
     return r
 

@@ -175,6 +175,38 @@ def test_timing_modes(small, path):
         lib.set_path(fps.PATH_AUTO)
 
 
+@pytest.mark.parametrize("path", [fps.PATH_SINGLE, fps.PATH_MFMA_F4, fps.PATH_POPCOUNT])
+def test_shard_merge(path):
+    """The multi-GPU design on one GPU: the library cut into 8 equal strides
+    (one per GPU), every query searched on each shard alone with global indices
+    (one batch: query i on shard s), the 8 top-k lists merged by (distance,
+    index): equal to the search over the whole library and to the oracle."""
+    n, G, k = 80_007, 8, 30
+    lib_np = fpsynth.make_library(n, 21)
+    cuts = [n * s // G for s in range(G + 1)]
+    lib = fps.Library(lib_np.words, strides=cuts)
+    qs = fpsynth.batch_queries(lib_np, 16, 22).words
+    rows = np.repeat(qs, G, axis=0)
+    masks = np.tile(np.array([1 << s for s in range(G)], dtype=np.uint32), len(qs))
+    lib.set_path(path)
+    try:
+        say("case: shard merge", path)
+        hits, off = lib.search_batch(rows, k, masks)
+    finally:
+        lib.set_path(fps.PATH_AUTO)
+    for i in range(len(qs)):
+        parts = []
+        for s in range(G):
+            h = hits[int(off[i * G + s]):int(off[i * G + s + 1])]
+            assert np.all((h["index"] >= cuts[s]) & (h["index"] < cuts[s + 1]))
+            parts.append(h)
+        allh = np.concatenate(parts)
+        merged = allh[np.lexsort((allh["index"], allh["distance"]))][:k]
+        whole = lib.search(qs[i], k)
+        assert np.array_equal(merged, whole), i
+        assert np.array_equal(whole, oracle.search(lib_np.words, qs[i], k)), i
+
+
 def test_autotuner_and_cache(tmp_path, monkeypatch):
     """AUTO times every candidate on the first batch of a shape, caches the
     winner (also in the FPS_TUNE_CACHE file), and a new handle reuses it."""
