@@ -115,12 +115,24 @@ __device__ __forceinline__ void hits_init(uint32_t lane, uint32_t *cnt) {
 
 struct HitBuf {
   RowInfo *row;    // the wave's rows
-  uint32_t *cnt;   // per row: hits since the last flush
+  uint32_t *cnt;   // per row: entries of the list being flushed
   uint32_t *base;  // per row: reservation of the flush
   uint32_t *sbase;
-  uint64_t *list;  // (row << 49) | (d << 41) | (rank << 32) | record index
+  uint64_t *list;  // (row << 40) | ((T + 1 - d) << 32) | record index
   uint32_t n;      // entries (wave-uniform)
 };
+
+// A list entry: local row lr, product u = d - T - 1 (negative), record g.
+__device__ __forceinline__ uint64_t hit_entry(uint32_t lr, int32_t u, uint32_t g) {
+  return ((uint64_t)lr << 40) | ((uint64_t)(uint32_t)(-u) << 32) | g;
+}
+
+// Waits for this wave's LDS operations; the clobber keeps the compiler from
+// moving memory accesses across.  The lanes of a wave run in lockstep, so the
+// wave's later LDS reads see what its earlier LDS writes and atomics left.
+__device__ __forceinline__ void lds_wave_fence() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
 
 // Loads the RowInfo of rows row0 .. row0 + ROWS - 1 of query block qb.
 template <int ROWS>
@@ -148,11 +160,28 @@ __device__ __forceinline__ void hits_rows(const Workspace &ws, const QBlock &qb,
   }
 }
 
-// Rows with a nonzero count have their RowInfo loaded (a hit needs a row of
-// the current query block), so an empty list reads no RowInfo at all.
+// Moves the list to the candidate buffers: ranks within each row from LDS
+// atomics on the row counts, one reservation per row with entries (all in
+// flight together), then the stores.  Only rows with entries have their
+// RowInfo read (a hit needs a row of the current query block), so an empty
+// list reads no RowInfo at all.
 template <int ROWS>
 __device__ __forceinline__ void hits_flush(const Workspace &ws, uint32_t lane, HitBuf &hb) {
   if (hb.n == 0) return;
+  constexpr int kPer = (int)kHitCap / 64;
+  uint64_t e[kPer];
+  uint32_t rank[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const uint32_t i = lane + 64u * j;
+    e[j] = 0;
+    rank[j] = 0;
+    if (i < hb.n) {
+      e[j] = hb.list[i];
+      rank[j] = atomicAdd(hb.cnt + (uint32_t)(e[j] >> 40), 1u);
+    }
+  }
+  lds_wave_fence();
 #pragma unroll
   for (int k = 0; k < (ROWS + 63) / 64; ++k) {
     const uint32_t lr = lane + 64u * k;
@@ -167,39 +196,19 @@ __device__ __forceinline__ void hits_flush(const Workspace &ws, uint32_t lane, H
       }
     }
   }
-  for (uint32_t i = lane; i < hb.n; i += 64) {
-    const uint64_t e = hb.list[i];
-    const uint32_t lr = (uint32_t)(e >> 49), d = (uint32_t)(e >> 41) & 0xFFu;
-    const uint32_t rank = (uint32_t)(e >> 32) & 0x1FFu;
-    const RowInfo *ri = hb.row + lr;
-    const Resv rv{hb.base[lr], hb.sbase[lr]};
-    cand_put(ws, ri, blockIdx.x % ri->nseg, rv, rank, ((uint64_t)d << 32) | (uint32_t)e);
+  lds_wave_fence();
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const uint32_t i = lane + 64u * j;
+    if (i < hb.n) {
+      const uint32_t lr = (uint32_t)(e[j] >> 40);
+      const uint32_t d = hb.row[lr].T1 - ((uint32_t)(e[j] >> 32) & 0xFFu);
+      const RowInfo *ri = hb.row + lr;
+      const Resv rv{hb.base[lr], hb.sbase[lr]};
+      cand_put(ws, ri, blockIdx.x % ri->nseg, rv, rank[j], ((uint64_t)d << 32) | (uint32_t)e[j]);
+    }
   }
   hb.n = 0;
-}
-
-// Adds the lanes with hit set to the list: local row lr (the same for the 32
-// lanes of a half-wave, as in a matrix-core result tile), product u, record g.
-// Ranks within a row come from the half-wave's ballot; the row's count is
-// updated by the half-wave's first lane (the wave owns its counts).
-template <int ROWS>
-__device__ __forceinline__ void hits_add(const Workspace &ws, uint32_t lane, HitBuf &hb, bool hit,
-                                         uint32_t lr, int32_t u, uint64_t g) {
-  const uint64_t bal = __ballot(hit);
-  if (bal == 0) return;
-  if (hb.n + 64 > kHitCap) hits_flush<ROWS>(ws, lane, hb);
-  const uint32_t half = lane >> 5;
-  const uint32_t mine = (uint32_t)(bal >> (32 * half));
-  const uint32_t below = (uint32_t)((1ull << (lane & 31)) - 1ull);
-  const uint32_t c0 = hb.cnt[lr];
-  if (hit) {
-    const uint32_t rank = c0 + (uint32_t)__popc(mine & below);
-    const uint32_t d = (uint32_t)(u + (int32_t)hb.row[lr].T1);
-    hb.list[hb.n + rank_below(bal)] = ((uint64_t)lr << 49) | ((uint64_t)d << 41) |
-                                      ((uint64_t)rank << 32) | (uint32_t)g;
-  }
-  if (mine != 0 && (lane & 31) == 0) hb.cnt[lr] = c0 + (uint32_t)__popc(mine);
-  hb.n += (uint32_t)__popcll(bal);
 }
 
 // Block barrier for LDS traffic: this wave's LDS operations complete, then the

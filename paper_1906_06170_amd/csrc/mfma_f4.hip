@@ -166,44 +166,45 @@ __device__ __forceinline__ int32_t or_bits(const v16f (&acc)[MQ]) {
 
 // Adds the hits of one 32x32 result tile (column block c of stage st) to the
 // wave's hit list.  Lane layout of the result: column lane & 31, rows
-// 8 (e >> 2) + 4 (lane >> 5) + (e & 3) of element e.  A per-lane mask of the
-// negative elements, ORed over the wave, leaves only the elements with a hit
-// to visit.
+// 8 (e >> 2) + 4 (lane >> 5) + (e & 3) of element e.  Each lane folds the
+// signs of its elements into a mask; every round then takes the lowest set bit
+// of each lane that has one (its element picked by a select tree over the
+// bits of its position) and appends those lanes with one ballot.  Rows past
+// the block's queries and records past the stage never pass (their products
+// start positive), so no further check is needed.
 template <int MQ>
-__device__ __forceinline__ void decode_f4(const Workspace &ws, const QBlock &qb, const Stage &st,
-                                          int c, uint32_t row0, uint32_t lane,
-                                          const v16f (&acc)[MQ], HitBuf &hb) {
-  static_assert(MQ * 16 <= 64, "one bit per result element");
-  const uint64_t g = st.g0 + 32 * c + (lane & 31);
-  const uint32_t half = lane >> 5;
-  const bool col_ok = g < st.g1;
+__device__ __forceinline__ void decode_f4(const Workspace &ws, const Stage &st, int c,
+                                          uint32_t lane, const v16f (&acc)[MQ], HitBuf &hb) {
+  constexpr int kE = MQ * 16;
+  static_assert(kE <= 64, "one bit per result element");
+  const uint32_t g = (uint32_t)(st.g0 + 32 * c + (lane & 31));
+  const uint32_t rowh = 4 * (lane >> 5);
   uint64_t m = 0;
 #pragma unroll
   for (int mq = 0; mq < MQ; ++mq)
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const float x = acc[mq][e];
-      m |= (uint64_t)(x < 0.0f ? 1u : 0u) << (16 * mq + e);
+    for (int e = 0; e < 16; ++e)
+      m |= (uint64_t)(acc[mq][e] < 0.0f ? 1u : 0u) << (16 * mq + e);
+  for (;;) {
+    const bool has = m != 0;
+    const uint64_t bal = __ballot(has);
+    if (bal == 0) break;
+    if (hb.n + 64 > kHitCap) hits_flush<MQ * 32>(ws, lane, hb);
+    if (has) {
+      const uint32_t b = (uint32_t)__builtin_ctzll(m);
+      m &= m - 1;
+      float v[kE];
+#pragma unroll
+      for (int i = 0; i < kE; ++i) v[i] = acc[i >> 4][i & 15];
+#pragma unroll
+      for (int l = 0, w = kE; w > 1; ++l, w >>= 1)
+#pragma unroll
+        for (int i = 0; i < w / 2; ++i) v[i] = ((b >> l) & 1u) ? v[2 * i + 1] : v[2 * i];
+      const uint32_t e = b & 15u;
+      const uint32_t lr = 32 * (b >> 4) + 8 * (e >> 2) + rowh + (e & 3u);
+      hb.list[hb.n + rank_below(bal)] = hit_entry(lr, (int32_t)v[0], g);
     }
-  if (!col_ok) m = 0;
-  uint64_t any = m;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) any |= __shfl_xor(any, o);
-  any = __builtin_amdgcn_readfirstlane((uint32_t)any) |
-        ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(any >> 32)) << 32);
-  while (any) {
-    const int b = __builtin_ctzll(any);
-    any &= any - 1;
-    const int mq = b >> 4, e = b & 15;
-    const uint32_t lr = mq * 32 + 8 * (e >> 2) + 4 * half + (e & 3);
-    const bool hit = ((m >> b) & 1u) != 0 && row0 + lr < qb.count;
-    float u = 0.0f;  // acc[mq][e], selected with constant indices only
-#pragma unroll
-    for (int k = 0; k < MQ; ++k)
-#pragma unroll
-      for (int f = 0; f < 16; ++f)
-        if (k == mq && f == e) u = acc[k][f];
-    hits_add<MQ * 32>(ws, lane, hb, hit, lr, (int32_t)u, g);
+    hb.n += (uint32_t)__popcll(bal);
   }
 }
 
@@ -233,7 +234,7 @@ __device__ __forceinline__ void stage_f4(const Workspace &ws, const QBlock &qb, 
       v16f acc[MQ];
       load_b_f4<MQ>(buf, c, lane, B);
       multiply_f4<MQ>(A, B, C, acc);
-      if (__ballot(or_bits<MQ>(acc) < 0) != 0) decode_f4<MQ>(ws, qb, st, c, row0, lane, acc, hb);
+      if (__ballot(or_bits<MQ>(acc) < 0) != 0) decode_f4<MQ>(ws, st, c, lane, acc, hb);
     }
     return;
   }
@@ -267,7 +268,7 @@ __device__ __forceinline__ void stage_f4(const Workspace &ws, const QBlock &qb, 
       v16f acc[MQ];
       load_b_f4<MQ>(buf, c, lane, B0);
       multiply_f4<MQ>(A, B0, C, acc);
-      decode_f4<MQ>(ws, qb, st, c, row0, lane, acc, hb);
+      decode_f4<MQ>(ws, st, c, lane, acc, hb);
     }
   }
 }
