@@ -238,38 +238,25 @@ __device__ __forceinline__ void stage_f4(const Workspace &ws, const QBlock &qb, 
     }
     return;
   }
-  // First pass: every column block, the sign test folded into a per-lane mask
-  // of column blocks with a negative result.  Then only those blocks are
-  // multiplied again and decoded.
-  // Software-pipelined: the products of column block c + 1 are issued before
-  // the sign test of block c, so the test and the next fragment reads overlap
-  // matrix-core work.
-  uint32_t hit_cols = 0;
+  // Every column block, software-pipelined: the products of block c + 1 are
+  // issued before the sign test of block c, so the test and the next fragment
+  // reads overlap matrix-core work.  A block with a negative result is decoded
+  // from the accumulators at hand (the branch is wave-uniform and rare).
   v8i B0[3], B1[3];
   v16f acc0[MQ], acc1[MQ];
   load_b_f4<MQ>(buf, 0, lane, B0);
   multiply_f4<MQ>(A, B0, C, acc0);
   load_b_f4<MQ>(buf, 1, lane, B1);
-#pragma unroll
+#pragma unroll 1
   for (int c = 0; c < kCols; c += 2) {
     multiply_f4<MQ>(A, B1, C, acc1);  // block c + 1
     if (c + 2 < kCols) load_b_f4<MQ>(buf, c + 2, lane, B0);
-    hit_cols |= (or_bits<MQ>(acc0) < 0 ? 1u : 0u) << c;
+    if (__ballot(or_bits<MQ>(acc0) < 0) != 0) decode_f4<MQ>(ws, st, c, lane, acc0, hb);
     if (c + 2 < kCols) {
       multiply_f4<MQ>(A, B0, C, acc0);  // block c + 2
       load_b_f4<MQ>(buf, c + 3, lane, B1);
     }
-    hit_cols |= (or_bits<MQ>(acc1) < 0 ? 1u : 0u) << (c + 1);
-  }
-  if (__ballot(hit_cols != 0) != 0) {
-#pragma unroll 1
-    for (int c = 0; c < kCols; ++c) {
-      if (__ballot((hit_cols >> c) & 1u) == 0) continue;
-      v16f acc[MQ];
-      load_b_f4<MQ>(buf, c, lane, B0);
-      multiply_f4<MQ>(A, B0, C, acc);
-      decode_f4<MQ>(ws, st, c, lane, acc, hb);
-    }
+    if (__ballot(or_bits<MQ>(acc1) < 0) != 0) decode_f4<MQ>(ws, st, c + 1, lane, acc1, hb);
   }
 }
 
