@@ -319,7 +319,8 @@ def serve(lib, lib_np, args, fps, fpsynth):
         nreq = len(arr)
         allq = fpsynth.batch_queries(lib_np, int(sizes.sum()), 1006).words
         offs = np.concatenate([[0], np.cumsum(sizes)])
-        srv = fps.Server(lib, pool_bytes=6 << 30, max_batch_queries=1024, n_streams=3)
+        srv = fps.Server(lib, pool_bytes=6 << 30, max_batch_queries=1024, n_streams=2,
+                         deadline_cap=True)
         tickets = [None] * nreq
         done = threading.Event()
 
@@ -354,7 +355,10 @@ def serve(lib, lib_np, args, fps, fpsynth):
              "p50_ms": st["p50_us"] / 1000, "p99_ms": st["p99_us"] / 1000,
              "max_ms": st["max_us"] / 1000, "deadline_miss_rate":
                  st["deadline_misses"] / max(1, st["requests"]),
-             "mean_batch_queries": st["mean_batch_queries"], "batches": int(st["batches"])}
+             "mean_batch_queries": st["mean_batch_queries"], "batches": int(st["batches"]),
+             "n_streams": 2, "max_batch_queries": 1024, "deadline_cap": True,
+             "service_model_us": [round(st["cost_fixed_us"], 1),
+                                  round(st["cost_per_weight_us"], 3)]}
         res[str(int(rate))] = r
         log("serve:", json.dumps(r))
     return res

@@ -248,7 +248,11 @@ typedef struct {
   uint32_t max_batch_queries; /* cap on queries coalesced into one batch */
   uint32_t max_wait_us;       /* longest a request waits for others to join its batch */
   uint32_t n_streams;         /* batches in flight at once (1..8) */
-  uint32_t reserved;
+  uint32_t deadline_cap;      /* nonzero: a batch stops growing before its predicted completion
+                                 passes the earliest deadline among its requests, unless that
+                                 deadline is missed anyway (the queue is behind); completion is
+                                 predicted by a linear model of batch service time fitted to the
+                                 batches served so far (fps_server_stats reports it) */
 } fps_server_config;
 
 typedef struct {
@@ -265,6 +269,8 @@ typedef struct {
   uint64_t batches;
   uint64_t deadline_misses;
   double p50_us, p99_us, max_us, mean_batch_queries;
+  double cost_fixed_us;      /* fitted service time of a batch: cost_fixed_us + */
+  double cost_per_weight_us; /* cost_per_weight_us * sum of q * (1 + k / 700) over its requests */
 } fps_server_stats;
 
 /*

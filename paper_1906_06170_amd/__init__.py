@@ -51,7 +51,7 @@ class SearchStats(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("pool_bytes", ctypes.c_size_t), ("max_batch_queries", ctypes.c_uint32),
                 ("max_wait_us", ctypes.c_uint32), ("n_streams", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("deadline_cap", ctypes.c_uint32)]
 
 
 class RequestStats(ctypes.Structure):
@@ -64,7 +64,8 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("requests", ctypes.c_uint64), ("queries", ctypes.c_uint64),
                 ("batches", ctypes.c_uint64), ("deadline_misses", ctypes.c_uint64),
                 ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
-                ("max_us", ctypes.c_double), ("mean_batch_queries", ctypes.c_double)]
+                ("max_us", ctypes.c_double), ("mean_batch_queries", ctypes.c_double),
+                ("cost_fixed_us", ctypes.c_double), ("cost_per_weight_us", ctypes.c_double)]
 
 
 EXPORTS = {
@@ -306,12 +307,12 @@ class Server:
     """Continuous-batching request loop over a Library (Sections 3.1, 4.4)."""
 
     def __init__(self, library: Library, pool_bytes: int, max_batch_queries: int = 512,
-                 max_wait_us: int = 0, n_streams: int = 2):
+                 max_wait_us: int = 0, n_streams: int = 2, deadline_cap: bool = True):
         torch = _require_gpu()
         self._lib = library
         self._ws = torch.empty(int(pool_bytes), dtype=torch.uint8, device="cuda")
         cfg = ServerConfig(int(pool_bytes), int(max_batch_queries), int(max_wait_us),
-                           int(n_streams), 0)
+                           int(n_streams), int(bool(deadline_cap)))
         self._h = ctypes.c_void_p()
         _check(load_library().fps_server_create(library.handle, ctypes.byref(cfg),
                                                 ctypes.c_void_p(self._ws.data_ptr()),

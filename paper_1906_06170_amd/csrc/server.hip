@@ -20,6 +20,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "batcher.h"
 #include "fps_internal.h"
 #include "runtime.h"
 
@@ -51,6 +52,10 @@ struct Slot {
   size_t ws_bytes = 0;
   SearchCtx ctx;
   std::thread worker;
+  // batch buffers, kept across batches
+  std::vector<uint64_t> qs, off;
+  std::vector<uint32_t> kk, mm;
+  std::vector<fps_hit> hits;
 };
 
 }  // namespace
@@ -67,6 +72,7 @@ struct fps_server {
   uint64_t next_ticket = 1;
   uint32_t next_batch = 1;
   bool stopping = false;
+  fps::CostModel cost;  // service time of a batch (batcher.h)
   // statistics
   std::vector<double> lat_us;
   uint64_t st_requests = 0, st_queries = 0, st_batches = 0, st_misses = 0, st_batch_q = 0;
@@ -100,34 +106,62 @@ static void run_slot(fps_server *S, Slot *slot) {
         }
         if (S->pending.empty()) continue;
       }
-      // first come, first served, while the batch fits the slot
-      uint32_t qsum = 0;
-      std::vector<uint32_t> kk, mm;
-      while (!S->pending.empty()) {
-        auto &r = S->pending.front();
-        if (!batch.empty() && qsum + r->q > S->cfg.max_batch_queries) break;
-        kk.insert(kk.end(), r->q, r->k);
-        mm.insert(mm.end(), r->q, r->mask);
-        Plan P;
-        if (!batch.empty() &&
-            (fps_plan(S->lib, qsum + r->q, kk.data(), mm.data(), &P) != FPS_OK ||
-             P.total_bytes > slot->ws_bytes)) {
-          kk.resize(qsum);
-          mm.resize(qsum);
-          break;
+      // a prefix of the queue (batcher.h), shrunk until it fits the slot
+      size_t n = fps::batch_prefix(
+          S->pending.size(),
+          [&](size_t i) {
+            const Request &r = *S->pending[i];
+            fps::PendingView v;
+            v.q = r.q;
+            v.k = r.k;
+            v.submit_ns = r.submit_ns;
+            v.deadline_us = r.deadline_us;
+            return v;
+          },
+          now_ns(), S->cfg.max_batch_queries, S->cfg.deadline_cap != 0, S->cost);
+      auto fits = [&](size_t m) {
+        slot->kk.clear();
+        slot->mm.clear();
+        for (size_t i = 0; i < m; ++i) {
+          const Request &r = *S->pending[i];
+          slot->kk.insert(slot->kk.end(), r.q, r.k);
+          slot->mm.insert(slot->mm.end(), r.q, r.mask);
         }
-        qsum += r->q;
-        batch.push_back(r);
+        Plan P;
+        return fps_plan(S->lib, (uint32_t)slot->kk.size(), slot->kk.data(), slot->mm.data(),
+                        &P) == FPS_OK &&
+               P.total_bytes <= slot->ws_bytes;
+      };
+      if (n > 1 && !fits(n)) {
+        // the longest prefix that fits (one request always does: admission)
+        size_t lo = 1, hi = n - 1;
+        while (lo < hi) {
+          const size_t mid = (lo + hi + 1) / 2;
+          if (fits(mid))
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        n = lo;
+      }
+      for (size_t i = 0; i < n; ++i) {
+        batch.push_back(S->pending.front());
         S->pending.pop_front();
       }
       if (!S->pending.empty()) S->cv_work.notify_one();
     }
     // run the batch
     uint32_t qsum = 0;
-    for (auto &r : batch) qsum += r->q;
-    std::vector<uint64_t> qs;
-    std::vector<uint32_t> kk, mm;
-    qs.reserve((size_t)qsum * 3);
+    double weight = 0;
+    for (auto &r : batch) {
+      qsum += r->q;
+      weight += fps::CostModel::weight(r->q, r->k);
+    }
+    std::vector<uint64_t> &qs = slot->qs;
+    std::vector<uint32_t> &kk = slot->kk, &mm = slot->mm;
+    qs.clear();
+    kk.clear();
+    mm.clear();
     uint64_t cap = 0;
     for (auto &r : batch) {
       qs.insert(qs.end(), r->queries.begin(), r->queries.end());
@@ -135,8 +169,10 @@ static void run_slot(fps_server *S, Slot *slot) {
       mm.insert(mm.end(), r->q, r->mask);
       cap += (uint64_t)r->q * r->k;
     }
-    std::vector<fps_hit> hits(std::max<uint64_t>(cap, 1));
-    std::vector<uint64_t> off(qsum + 1);
+    if (slot->hits.size() < std::max<uint64_t>(cap, 1)) slot->hits.resize(std::max<uint64_t>(cap, 1));
+    if (slot->off.size() < (size_t)qsum + 1) slot->off.resize((size_t)qsum + 1);
+    fps_hit *hits = slot->hits.data();
+    uint64_t *off = slot->off.data();
     const uint64_t t0 = now_ns();
     uint32_t bid;
     {
@@ -145,8 +181,8 @@ static void run_slot(fps_server *S, Slot *slot) {
     }
     fps_clear_error();
     fps_status rc = fps_search_impl(S->lib, &slot->ctx, qs.data(), qsum, kk.data(), mm.data(),
-                                    slot->ws, slot->ws_bytes, hits.data(), cap, off.data(),
-                                    slot->stream, FPS_PATH_AUTO);
+                                    slot->ws, slot->ws_bytes, hits, cap, off, slot->stream,
+                                    FPS_PATH_AUTO);
     const std::string err = rc ? std::string(fps_last_error()) : std::string();
     const uint64_t t1 = now_ns();
     {
@@ -163,7 +199,7 @@ static void run_slot(fps_server *S, Slot *slot) {
           r->offsets.resize(r->q + 1);
           const uint64_t h0 = off[base];
           for (uint32_t i = 0; i <= r->q; ++i) r->offsets[i] = off[base + i] - h0;
-          r->hits.assign(hits.begin() + h0, hits.begin() + off[base + r->q]);
+          r->hits.assign(hits + h0, hits + off[base + r->q]);
         }
         base += r->q;
         r->done = true;
@@ -176,6 +212,7 @@ static void run_slot(fps_server *S, Slot *slot) {
       }
       S->st_batches++;
       S->st_batch_q += qsum;
+      if (!rc) S->cost.observe(weight, (double)(t1 - t0) / 1000.0);
     }
     S->cv_done.notify_all();
     S->cv_room.notify_all();
@@ -300,6 +337,8 @@ extern "C" fps_status fps_server_stats_get(fps_server *srv, fps_server_stats *st
   st->batches = srv->st_batches;
   st->deadline_misses = srv->st_misses;
   st->mean_batch_queries = srv->st_batches ? (double)srv->st_batch_q / srv->st_batches : 0.0;
+  st->cost_fixed_us = srv->cost.c0_us();
+  st->cost_per_weight_us = srv->cost.c1_us();
   if (!srv->lat_us.empty()) {
     std::vector<double> v = srv->lat_us;
     std::sort(v.begin(), v.end());
