@@ -319,8 +319,8 @@ def serve(lib, lib_np, args, fps, fpsynth):
         nreq = len(arr)
         allq = fpsynth.batch_queries(lib_np, int(sizes.sum()), 1006).words
         offs = np.concatenate([[0], np.cumsum(sizes)])
-        srv = fps.Server(lib, pool_bytes=6 << 30, max_batch_queries=1024, n_streams=2,
-                         deadline_cap=True)
+        srv = fps.Server(lib, pool_bytes=6 << 30, max_batch_queries=1024, n_streams=3,
+                         deadline_cap=True, reserve_streams=1)
         tickets = [None] * nreq
         done = threading.Event()
 
@@ -356,7 +356,8 @@ def serve(lib, lib_np, args, fps, fpsynth):
              "max_ms": st["max_us"] / 1000, "deadline_miss_rate":
                  st["deadline_misses"] / max(1, st["requests"]),
              "mean_batch_queries": st["mean_batch_queries"], "batches": int(st["batches"]),
-             "n_streams": 2, "max_batch_queries": 1024, "deadline_cap": True,
+             "n_streams": 3, "reserve_streams": 1, "max_batch_queries": 1024,
+             "deadline_cap": True,
              "service_model_us": [round(st["cost_fixed_us"], 1),
                                   round(st["cost_per_weight_us"], 3)]}
         res[str(int(rate))] = r

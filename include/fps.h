@@ -253,6 +253,11 @@ typedef struct {
                                  deadline is missed anyway (the queue is behind); completion is
                                  predicted by a linear model of batch service time fitted to the
                                  batches served so far (fps_server_stats reports it) */
+  uint32_t reserve_streams;   /* of the n_streams, how many take a batch only under overload: at
+                                 least max_batch_queries queries wait and the first request would
+                                 miss its deadline even if served now; < n_streams.  At light load
+                                 fewer batches then share the GPU; under overload the extra
+                                 batches keep it busy between the phases of the others */
 } fps_server_config;
 
 typedef struct {

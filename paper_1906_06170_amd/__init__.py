@@ -51,7 +51,7 @@ class SearchStats(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("pool_bytes", ctypes.c_size_t), ("max_batch_queries", ctypes.c_uint32),
                 ("max_wait_us", ctypes.c_uint32), ("n_streams", ctypes.c_uint32),
-                ("deadline_cap", ctypes.c_uint32)]
+                ("deadline_cap", ctypes.c_uint32), ("reserve_streams", ctypes.c_uint32)]
 
 
 class RequestStats(ctypes.Structure):
@@ -300,19 +300,22 @@ class Library:
             self._handle, _ptr(qs), nq, _ptr(kk), None if mm is None else _ptr(mm),
             ctypes.c_void_p(ws.data_ptr()), ws.numel(), _ptr(out), cap, _ptr(off),
             _stream(stream, self._device)))
-        return out[:int(off[-1])].copy(), off
+        # a view (no second copy of up to sum(k) hits); it is the whole array
+        # unless some query has fewer than k records in its strides
+        return out[:int(off[-1])], off
 
 
 class Server:
     """Continuous-batching request loop over a Library (Sections 3.1, 4.4)."""
 
     def __init__(self, library: Library, pool_bytes: int, max_batch_queries: int = 512,
-                 max_wait_us: int = 0, n_streams: int = 2, deadline_cap: bool = True):
+                 max_wait_us: int = 0, n_streams: int = 2, deadline_cap: bool = True,
+                 reserve_streams: int = 0):
         torch = _require_gpu()
         self._lib = library
         self._ws = torch.empty(int(pool_bytes), dtype=torch.uint8, device="cuda")
         cfg = ServerConfig(int(pool_bytes), int(max_batch_queries), int(max_wait_us),
-                           int(n_streams), int(bool(deadline_cap)))
+                           int(n_streams), int(bool(deadline_cap)), int(reserve_streams))
         self._h = ctypes.c_void_p()
         _check(load_library().fps_server_create(library.handle, ctypes.byref(cfg),
                                                 ctypes.c_void_p(self._ws.data_ptr()),

@@ -10,6 +10,10 @@
 //     is behind), the deadline no longer limits the batch: under overload the
 //     larger batch clears the queue sooner.
 // The caller then shrinks the prefix until its workspace fits a slot.
+// Reserve slots (the last reserve_streams of the server's streams) take a
+// batch only under overload (reserve_may_run): at light load fewer batches
+// share the GPU and each finishes sooner; under overload the extra batch in
+// flight fills the gaps between the phases of the others.
 //
 // Completion is predicted by a linear model of service time fitted online to
 // the batches served so far: time = c0 + c1 * x, x = sum over requests of
@@ -69,6 +73,22 @@ class CostModel {
   double c0_ = 500.0, c1_ = 20.0;
   double sw_ = 0, sx_ = 0, sy_ = 0, sxx_ = 0, sxy_ = 0;
 };
+
+// The queue is behind when its first request would miss its deadline even if
+// it were served alone starting now (requests without a deadline never are).
+inline bool queue_behind(const PendingView &head, uint64_t now_ns, const CostModel &cm) {
+  if (!head.deadline_us) return false;
+  return now_ns + cm.predict_ns(CostModel::weight(head.q, head.k)) >
+         head.submit_ns + 1000ull * head.deadline_us;
+}
+
+// A reserve slot takes a batch only under overload: the queue is behind and
+// holds at least a full batch of queries (a late request alone, at light
+// load, does not wake it).
+inline bool reserve_may_run(const PendingView &head, uint64_t pending_queries,
+                            uint32_t max_queries, uint64_t now_ns, const CostModel &cm) {
+  return pending_queries >= max_queries && queue_behind(head, now_ns, cm);
+}
 
 // Length of the queue prefix that forms the next batch (at least 1 when the
 // queue is not empty).  get(i) returns the PendingView of the i-th request.

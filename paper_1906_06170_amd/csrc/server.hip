@@ -67,6 +67,7 @@ struct fps_server {
   std::mutex mu;
   std::condition_variable cv_work, cv_done, cv_room;
   std::deque<std::shared_ptr<Request>> pending;
+  uint64_t pending_q = 0;  // queries in pending
   std::unordered_map<uint64_t, std::shared_ptr<Request>> live;
   size_t admitted_bytes = 0;
   uint64_t next_ticket = 1;
@@ -85,13 +86,32 @@ static size_t request_bytes(fps_library *lib, uint32_t q, uint32_t k, uint32_t m
   return P.total_bytes;
 }
 
-static void run_slot(fps_server *S, Slot *slot) {
+static fps::PendingView view_of(const Request &r) {
+  fps::PendingView v;
+  v.q = r.q;
+  v.k = r.k;
+  v.submit_ns = r.submit_ns;
+  v.deadline_us = r.deadline_us;
+  return v;
+}
+
+static void run_slot(fps_server *S, Slot *slot, bool reserve) {
   (void)hipSetDevice(S->lib->device);
   for (;;) {
     std::vector<std::shared_ptr<Request>> batch;
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      S->cv_work.wait(lk, [&] { return S->stopping || !S->pending.empty(); });
+      auto ready = [&] {
+        if (S->stopping || S->pending.empty()) return S->stopping;
+        return !reserve || fps::reserve_may_run(view_of(*S->pending.front()), S->pending_q,
+                                                S->cfg.max_batch_queries, now_ns(), S->cost);
+      };
+      if (reserve) {
+        // the queue can fall behind without a notification: look again
+        while (!ready()) S->cv_work.wait_for(lk, std::chrono::microseconds(500));
+      } else {
+        S->cv_work.wait(lk, ready);
+      }
       if (S->pending.empty() && S->stopping) return;
       if (S->cfg.max_wait_us > 0) {
         // give a small batch a bounded chance to grow
@@ -108,17 +128,8 @@ static void run_slot(fps_server *S, Slot *slot) {
       }
       // a prefix of the queue (batcher.h), shrunk until it fits the slot
       size_t n = fps::batch_prefix(
-          S->pending.size(),
-          [&](size_t i) {
-            const Request &r = *S->pending[i];
-            fps::PendingView v;
-            v.q = r.q;
-            v.k = r.k;
-            v.submit_ns = r.submit_ns;
-            v.deadline_us = r.deadline_us;
-            return v;
-          },
-          now_ns(), S->cfg.max_batch_queries, S->cfg.deadline_cap != 0, S->cost);
+          S->pending.size(), [&](size_t i) { return view_of(*S->pending[i]); }, now_ns(),
+          S->cfg.max_batch_queries, S->cfg.deadline_cap != 0, S->cost);
       auto fits = [&](size_t m) {
         slot->kk.clear();
         slot->mm.clear();
@@ -145,10 +156,11 @@ static void run_slot(fps_server *S, Slot *slot) {
         n = lo;
       }
       for (size_t i = 0; i < n; ++i) {
+        S->pending_q -= S->pending.front()->q;
         batch.push_back(S->pending.front());
         S->pending.pop_front();
       }
-      if (!S->pending.empty()) S->cv_work.notify_one();
+      if (!S->pending.empty()) S->cv_work.notify_all();
     }
     // run the batch
     uint32_t qsum = 0;
@@ -226,6 +238,8 @@ extern "C" fps_status fps_server_create(fps_library *lib, const fps_server_confi
   if (cfg->n_streams < 1 || cfg->n_streams > 8)
     return fps_fail(FPS_E_ARG, "n_streams must be 1..8");
   if (cfg->max_batch_queries < 1) return fps_fail(FPS_E_ARG, "max_batch_queries must be >= 1");
+  if (cfg->reserve_streams >= cfg->n_streams)
+    return fps_fail(FPS_E_ARG, "reserve_streams must be below n_streams");
   if (cfg->pool_bytes == 0 || cfg->pool_bytes > ws_bytes)
     return fps_fail(FPS_E_ARG, "pool_bytes must be in 1..ws_bytes");
   if (((uintptr_t)workspace & 255) != 0)
@@ -247,7 +261,9 @@ extern "C" fps_status fps_server_create(fps_library *lib, const fps_server_confi
     }
     S->slots.push_back(std::move(sl));
   }
-  for (auto &sl : S->slots) sl->worker = std::thread(run_slot, S.get(), sl.get());
+  for (uint32_t i = 0; i < cfg->n_streams; ++i)
+    S->slots[i]->worker = std::thread(run_slot, S.get(), S->slots[i].get(),
+                                      i >= cfg->n_streams - cfg->reserve_streams);
   *out = S.release();
   return FPS_OK;
 }
@@ -288,9 +304,10 @@ extern "C" fps_status fps_server_submit(fps_server *srv, const uint64_t *queries
   r->submit_ns = now_ns();
   srv->live[r->ticket] = r;
   srv->pending.push_back(r);
+  srv->pending_q += q;
   *ticket = r->ticket;
   lk.unlock();
-  srv->cv_work.notify_one();
+  srv->cv_work.notify_all();  // a reserve slot may take the wake-up and stay idle
   return FPS_OK;
 }
 

@@ -77,5 +77,23 @@ int main() {
   }
   // k raises the weight: k = 700 doubles it -> 300 + 80 n <= 10000 -> n <= 121
   std::printf("deadline_k700 %zu\n", prefix(reqs(400, 10, 700, now, 10000), now, 100000, true, lin));
+  // behind: the head alone (300 + 40 us) misses its deadline
+  {
+    PendingView h;
+    h.q = 10;
+    h.k = 0;
+    h.deadline_us = 10000;
+    h.submit_ns = now - 9000000ull;  // 1 ms left: 340 us fit
+    std::printf("behind_no %d\n", fps::queue_behind(h, now, lin) ? 1 : 0);
+    h.submit_ns = now - 9800000ull;  // 200 us left: 340 us do not
+    std::printf("behind_yes %d\n", fps::queue_behind(h, now, lin) ? 1 : 0);
+    h.deadline_us = 0;  // no deadline: never behind
+    std::printf("behind_none %d\n", fps::queue_behind(h, now, lin) ? 1 : 0);
+    h.deadline_us = 10000;
+    std::printf("reserve_full %d\n", fps::reserve_may_run(h, 1024, 1024, now, lin) ? 1 : 0);
+    std::printf("reserve_short %d\n", fps::reserve_may_run(h, 1023, 1024, now, lin) ? 1 : 0);
+    h.submit_ns = now;  // on time
+    std::printf("reserve_on_time %d\n", fps::reserve_may_run(h, 5000, 1024, now, lin) ? 1 : 0);
+  }
   return 0;
 }

@@ -1,6 +1,7 @@
 """The serving loop's batch-formation policy (csrc/batcher.h), compiled by the
 host compiler alone and driven through fixed scenarios: the online service-time
-fit, the query cap, the deadline cap and its release when the queue is behind."""
+fit, the query cap, the deadline cap and its release when the queue is behind,
+and the test that wakes reserve slots."""
 import os
 import shutil
 import subprocess
@@ -65,3 +66,15 @@ def test_deadline_request_joins_only_while_met(results):
     # at position 10 it fits (300 + 40 * 11 = 740 us); later requests join while
     # 300 + 40 n <= 1000, i.e. n <= 17
     assert results["early_joiner"] == 17
+
+
+def test_queue_behind(results):
+    assert results["behind_no"] == 0
+    assert results["behind_yes"] == 1
+    assert results["behind_none"] == 0
+
+
+def test_reserve_slots_wait_for_overload(results):
+    assert results["reserve_full"] == 1      # behind, a full batch waiting
+    assert results["reserve_short"] == 0     # behind, but less than a batch
+    assert results["reserve_on_time"] == 0   # a full batch, but on time
