@@ -325,10 +325,11 @@ fps_status fps_make_rangeset(const fps_library *lib, uint32_t mask, RangeSet *rs
 // (b1 = G * S1, b2 = G * b1, ...), and after each phase the bound is refined to
 // the keff-th smallest distance of the prefix scanned so far.  A phase
 // [b_i, b_i+1) then appends about keff * (b_i+1 - b_i) / b_i records, times a
-// small factor for ties at the bound.  G = A / keff clamped to 8..64, with
-// A = 4096 for batches of <= kSegQueries queries (appends are cheap there and a
-// phase costs a launch) and A = 256 for larger batches, whose matrix-core
-// scans pay for every append with a decode of the result tile.
+// small factor for ties at the bound.  G = A / keff clamped to Gmin..64, with
+// A = 4096 and Gmin = 8 for batches of <= kSegQueries queries (appends are
+// cheap there and a phase costs a launch) and A = 256, Gmin = 4 for larger
+// batches, whose matrix-core scans pay for every append with a decode of the
+// result tile.
 static std::vector<uint64_t> phase_bounds(const fps_library *lib, uint64_t max_neff,
                                           uint64_t max_keff, uint64_t s1, uint32_t q) {
   std::vector<uint64_t> b{0};
@@ -338,7 +339,9 @@ static std::vector<uint64_t> phase_bounds(const fps_library *lib, uint64_t max_n
     return b;
   }
   const uint64_t A = q <= kSegQueries ? 4096 : 256;
-  const uint64_t G = std::min<uint64_t>(64, std::max<uint64_t>(8, A / std::max<uint64_t>(max_keff, 1)));
+  const uint64_t Gmin = q <= kSegQueries ? 8 : 4;
+  const uint64_t G =
+      std::min<uint64_t>(64, std::max<uint64_t>(Gmin, A / std::max<uint64_t>(max_keff, 1)));
   uint64_t a = lib->phase_a ? lib->phase_a : s1 * G;
   while (a < max_neff && b.size() < (size_t)kMaxPhases) {
     b.push_back(a);
