@@ -394,8 +394,14 @@ def test_errors(small):
     assert np.array_equal(lib.search(q, 30), oracle.search(lib_np.words, q, 30))
 
 
-def test_server_alone_vs_mix(small):
-    """Each request's answer is the same alone, in a mix and from the oracle."""
+@pytest.mark.parametrize("streams,reserve,cap,deadline_us,max_q", [
+    (3, 0, True, 10_000, 512),   # deadline cap, every stream always available
+    (3, 1, True, 1, 128),        # every request late at once: overload, reserve slot runs
+    (2, 0, False, 0, 512),       # no deadlines, no cap
+])
+def test_server_alone_vs_mix(small, streams, reserve, cap, deadline_us, max_q):
+    """Each request's answer is the same alone, in a mix and from the oracle,
+    under every batching policy of the server."""
     lib_np, lib = small
     rng = np.random.default_rng(5)
     reqs = []
@@ -405,9 +411,10 @@ def test_server_alone_vs_mix(small):
         k = int(rng.choice([30, 100, 1000]))
         m = int(rng.choice([1, 3, 7]))
         reqs.append((qs, k, m))
-    srv = fps.Server(lib, pool_bytes=512 << 20, max_batch_queries=512, n_streams=3)
+    srv = fps.Server(lib, pool_bytes=512 << 20, max_batch_queries=max_q, n_streams=streams,
+                     deadline_cap=cap, reserve_streams=reserve)
     try:
-        tickets = [srv.submit(qs, k, m, deadline_us=10_000) for qs, k, m in reqs]
+        tickets = [srv.submit(qs, k, m, deadline_us=deadline_us) for qs, k, m in reqs]
         mixed = [srv.wait(t, len(r[0]), r[1]) for t, r in zip(tickets, reqs)]
         st = srv.stats()
         assert st["requests"] == 40
@@ -418,5 +425,8 @@ def test_server_alone_vs_mix(small):
             assert np.array_equal(off, woff) and np.array_equal(h, want)
             assert np.array_equal(aoff, woff) and np.array_equal(alone, want)
         assert max(r[2]["batch_queries"] for r in mixed) > 64  # requests were coalesced
+        assert max(r[2]["batch_queries"] for r in mixed) <= max(max_q, 64)
+        if deadline_us == 1:
+            assert st["deadline_misses"] == 40  # a 1 us budget is always missed
     finally:
         srv.close()
