@@ -94,7 +94,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
-              "the engine has no multi-GPU path in this build", file=sys.stderr)
+              "the engine runs on one GPU and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     legs = set(args.only.split(",")) if args.only != "all" else {
         "single", "shard", "batch", "uneven", "serve", "cpu"}
