@@ -32,6 +32,7 @@ constexpr int kScanTile = 512;      // records per wave iteration of the single-
 constexpr int kBatchTile = 2048;    // records per work item of the batched kernels
 constexpr int kBoundChunk = 1024;   // least records per block of the bound kernel
 constexpr int kBoundBlocks = 128;   // most blocks per query block of the bound kernel
+constexpr int kBoundGrid = 1024;    // bound blocks aimed at once query blocks fill the GPU
 constexpr int kHistCopies = 8;      // bound histograms are spread over 8 copies per query
 constexpr uint64_t kDefaultBoundSample = 1ull << 16;  // records of the bound sample
 // One scan phase when the first bound is expected to admit at most this many

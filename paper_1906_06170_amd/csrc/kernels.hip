@@ -188,8 +188,13 @@ __global__ __launch_bounds__(256) void k_bound(Lib lib, Workspace ws, uint32_t c
 void launch_bound(const Lib &lib, const Workspace &ws, uint32_t nbblocks, uint64_t max_sample,
                   hipStream_t s) {
   if (nbblocks == 0) return;
-  // up to kBoundBlocks chunks of at least kBoundChunk records
-  uint64_t chunk = (max_sample + kBoundBlocks - 1) / kBoundBlocks;
+  // Up to kBoundBlocks chunks of at least kBoundChunk records, and fewer once
+  // the query blocks alone fill the GPU: every block adds its histograms into
+  // device memory with one atomic per nonzero bin, so more chunks than needed
+  // only multiply those atomics.
+  const uint64_t per_qb = std::max<uint64_t>(
+      1, std::min<uint64_t>(kBoundBlocks, (uint64_t)kBoundGrid / nbblocks));
+  uint64_t chunk = (max_sample + per_qb - 1) / per_qb;
   chunk = (chunk + kBoundChunk - 1) / kBoundChunk * kBoundChunk;
   uint32_t chunks = (uint32_t)((max_sample + chunk - 1) / chunk);
   if (chunks == 0) chunks = 1;

@@ -234,7 +234,7 @@ __device__ __forceinline__ void stage_f4(const Workspace &ws, const QBlock &qb, 
       v16f acc[MQ];
       load_b_f4<MQ>(buf, c, lane, B);
       multiply_f4<MQ>(A, B, C, acc);
-      if (__ballot(or_bits<MQ>(acc) < 0) != 0) decode_f4<MQ>(ws, st, c, lane, acc, hb);
+      if (__builtin_expect(__ballot(or_bits<MQ>(acc) < 0) != 0, 0)) decode_f4<MQ>(ws, st, c, lane, acc, hb);
     }
     return;
   }
@@ -251,12 +251,12 @@ __device__ __forceinline__ void stage_f4(const Workspace &ws, const QBlock &qb, 
   for (int c = 0; c < kCols; c += 2) {
     multiply_f4<MQ>(A, B1, C, acc1);  // block c + 1
     if (c + 2 < kCols) load_b_f4<MQ>(buf, c + 2, lane, B0);
-    if (__ballot(or_bits<MQ>(acc0) < 0) != 0) decode_f4<MQ>(ws, st, c, lane, acc0, hb);
+    if (__builtin_expect(__ballot(or_bits<MQ>(acc0) < 0) != 0, 0)) decode_f4<MQ>(ws, st, c, lane, acc0, hb);
     if (c + 2 < kCols) {
       multiply_f4<MQ>(A, B0, C, acc0);  // block c + 2
       load_b_f4<MQ>(buf, c + 3, lane, B1);
     }
-    if (__ballot(or_bits<MQ>(acc1) < 0) != 0) decode_f4<MQ>(ws, st, c + 1, lane, acc1, hb);
+    if (__builtin_expect(__ballot(or_bits<MQ>(acc1) < 0) != 0, 0)) decode_f4<MQ>(ws, st, c + 1, lane, acc1, hb);
   }
 }
 
