@@ -229,6 +229,39 @@ def test_autotuner_and_cache(tmp_path, monkeypatch):
     assert (st2["path"], st2["variant"]) == (st["path"], st["variant"])
 
 
+@pytest.fixture(scope="module")
+def wide_batch():
+    """12,000 queries over a ragged 6,000-record library with three strides: k
+    from {0, 1, 7, 30, 5,999, 6,000, 7,000} (0, and k at or beyond the records
+    of the query's strides, included) and every stride mask; the oracle's
+    answer is computed once."""
+    lib_np = fpsynth.make_library(6_000, 21)
+    strides = [0, 1_500, 4_100, 6_000]
+    lib = fps.Library(lib_np.words, strides=strides)
+    nq = 12_000
+    qs = fpsynth.batch_queries(lib_np, nq, 22).words
+    rng = np.random.default_rng(23)
+    k = rng.choice(np.array([0, 1, 7, 30, 5_999, 6_000, 7_000], dtype=np.uint32), nq,
+                   p=[0.05, 0.2, 0.3, 0.3, 0.05, 0.05, 0.05]).astype(np.uint32)
+    masks = rng.integers(1, 8, nq).astype(np.uint32)
+    want = oracle.search_batch(lib_np.words, qs, k, strides, masks)
+    return lib_np, lib, qs, k, masks, want
+
+
+@pytest.mark.parametrize("path", PATHS + [fps.PATH_AUTO])
+def test_wide_batch(wide_batch, path):
+    """More queries than any benchmark batch, every path against one oracle run."""
+    lib_np, lib, qs, k, masks, (ohits, ooff) = wide_batch
+    lib.set_path(path)
+    say("case: wide batch path", path, "q", len(qs))
+    try:
+        hits, off = lib.search_batch(qs, k, masks)
+    finally:
+        lib.set_path(fps.PATH_AUTO)
+    assert np.array_equal(off, ooff)
+    assert np.array_equal(hits, ohits)
+
+
 @pytest.mark.parametrize("path", PATHS)
 def test_all_masks_and_strides(small, path):
     lib_np, lib = small
