@@ -117,12 +117,10 @@ static void run_slot(fps_server *S, Slot *slot, bool reserve) {
         // give a small batch a bounded chance to grow
         const uint64_t oldest = S->pending.front()->submit_ns;
         const uint64_t until = oldest + (uint64_t)S->cfg.max_wait_us * 1000ull;
-        uint32_t have = 0;
-        for (auto &r : S->pending) have += r->q;
-        while (!S->stopping && have < S->cfg.max_batch_queries && now_ns() < until) {
-          S->cv_work.wait_for(lk, std::chrono::nanoseconds(until - now_ns()));
-          have = 0;
-          for (auto &r : S->pending) have += r->q;
+        while (!S->stopping && S->pending_q < S->cfg.max_batch_queries) {
+          const uint64_t now = now_ns();
+          if (now >= until) break;
+          S->cv_work.wait_for(lk, std::chrono::nanoseconds(until - now));
         }
         if (S->pending.empty()) continue;
       }

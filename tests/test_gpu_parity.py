@@ -427,12 +427,13 @@ def test_errors(small):
     assert np.array_equal(lib.search(q, 30), oracle.search(lib_np.words, q, 30))
 
 
-@pytest.mark.parametrize("streams,reserve,cap,deadline_us,max_q", [
-    (3, 0, True, 10_000, 512),   # deadline cap, every stream always available
-    (3, 1, True, 1, 128),        # every request late at once: overload, reserve slot runs
-    (2, 0, False, 0, 512),       # no deadlines, no cap
+@pytest.mark.parametrize("streams,reserve,cap,deadline_us,max_q,wait_us", [
+    (3, 0, True, 10_000, 512, 0),   # deadline cap, every stream always available
+    (3, 1, True, 1, 128, 0),        # every request late at once: overload, reserve slot runs
+    (2, 0, False, 0, 512, 0),       # no deadlines, no cap
+    (1, 0, True, 10_000, 512, 3_000),  # a batch waits up to 3 ms for more requests
 ])
-def test_server_alone_vs_mix(small, streams, reserve, cap, deadline_us, max_q):
+def test_server_alone_vs_mix(small, streams, reserve, cap, deadline_us, max_q, wait_us):
     """Each request's answer is the same alone, in a mix and from the oracle,
     under every batching policy of the server."""
     lib_np, lib = small
@@ -445,7 +446,7 @@ def test_server_alone_vs_mix(small, streams, reserve, cap, deadline_us, max_q):
         m = int(rng.choice([1, 3, 7]))
         reqs.append((qs, k, m))
     srv = fps.Server(lib, pool_bytes=512 << 20, max_batch_queries=max_q, n_streams=streams,
-                     deadline_cap=cap, reserve_streams=reserve)
+                     deadline_cap=cap, reserve_streams=reserve, max_wait_us=wait_us)
     try:
         tickets = [srv.submit(qs, k, m, deadline_us=deadline_us) for qs, k, m in reqs]
         mixed = [srv.wait(t, len(r[0]), r[1]) for t, r in zip(tickets, reqs)]
