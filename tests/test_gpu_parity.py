@@ -262,6 +262,36 @@ def test_wide_batch(wide_batch, path):
     assert np.array_equal(hits, ohits)
 
 
+@pytest.mark.parametrize("case", range(32))
+def test_random_combinations(case):
+    """Seeded random combinations of the dimensions tested one at a time
+    elsewhere: library size (ragged), stride cuts, batch size, per-query k
+    (0 to beyond n) and masks, on every path.  The case number names its seed."""
+    rng = np.random.default_rng(9000 + case)
+    n = int(rng.integers(1, 60_000))
+    nstr = int(rng.integers(1, 5))
+    cuts = sorted(set(int(c) for c in rng.integers(1, max(n, 2), nstr - 1))) if n > 1 else []
+    strides = [0] + [c for c in cuts if 0 < c < n] + [n]
+    lib_np = fpsynth.make_library(n, 9100 + case)
+    lib = fps.Library(lib_np.words, strides=strides)
+    ns = len(strides) - 1
+    nq = int(rng.integers(1, 700))
+    qs = fpsynth.batch_queries(lib_np, nq, 9200 + case).words
+    k = rng.choice(np.array([0, 1, 2, 5, 30, 100, 1000, n, n + 3], dtype=np.int64), nq)
+    k = np.minimum(k, 2 ** 31).astype(np.uint32)
+    masks = rng.integers(1, 2 ** ns, nq).astype(np.uint32)
+    say("case: random", case, "n", n, "strides", strides, "q", nq)
+    want, woff = oracle.search_batch(lib_np.words, qs, k, strides, masks)
+    for path in PATHS:
+        lib.set_path(path)
+        try:
+            hits, off = lib.search_batch(qs, k, masks)
+        finally:
+            lib.set_path(fps.PATH_AUTO)
+        assert np.array_equal(off, woff), (case, path)
+        assert np.array_equal(hits, want), (case, path)
+
+
 @pytest.mark.parametrize("path", PATHS)
 def test_all_masks_and_strides(small, path):
     lib_np, lib = small
