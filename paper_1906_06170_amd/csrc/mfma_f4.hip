@@ -7,14 +7,17 @@
 // partial sum is an integer below 2^9, so the fp32 accumulation is exact.
 //
 // Per (query, record) pair the product is u = d - T_q - 1 (a candidate iff
-// u < 0):
-//   key digits      : query -2 * q_s, record r_s      -> -2 q.r
-//   accumulator init: |q| - T_q - 1 per query row     (the MFMA's C input)
-//   |r| digits      : 7 spare digits; query 6,6,6,6,6,6,1, record the digits
-//                     v_0..v_5, w of |r| = 6 (v_0 + .. + v_5) + w (a per-|r|
-//                     table in LDS)
-// Invalid rows start at +300 and invalid records carry |r| digits worth 216,
-// so neither can pass.
+// u < 0), accumulated from zero (the MFMA's C input is the inline constant 0,
+// so no accumulator-input registers are needed):
+//   key digits  : query -2 * q_s, record r_s      -> -2 q.r
+//   |r| digits  : 7 spare digits; query 6,6,6,6,6,6,1, record the digits
+//                 v_0..v_5, w of |r| = 6 (v_0 + .. + v_5) + w (a per-|r|
+//                 table in LDS)
+//   bias digits : 7 more spare digits; record 6,6,6,6,6,6,1, query the digits
+//                 of B = |q| - T_q - 1 in the same form (negated digits for
+//                 B < 0)
+// Invalid rows carry B = 166 and invalid records |r| digits worth 216, so
+// neither can pass.
 //
 // Bit -> digit expansion: a 32-bit chunk of keys becomes 32 digits (16 bytes)
 // with four byte permutations (v_perm_b32) of a 4-entry table: output dword j,
@@ -22,7 +25,9 @@
 // Queries and records use the same order, which is all a dot product needs.
 // The six chunks of a record (lo a, hi a, lo b, hi b, c, d) are the six 16-byte
 // K fragments of its three MFMA K-steps; the |r| digits sit in dword 3 of the
-// d fragment, which holds bits 6, 7, 14, 15, ... of d (always zero).
+// d fragment, which holds bits 6, 7, 14, 15, ... of d (always zero), and the
+// bias digits in bytes 1..3 of dword 0 and byte 1 of dword 1 (bits 8..29 of d,
+// also zero).
 #include "mfma_common.h"
 
 namespace fps {
@@ -36,6 +41,9 @@ constexpr uint32_t kDigitsRecord = 0x22200200u;  // 2-bit index -> two digits of
 constexpr uint32_t kDigitsQuery = 0xCCC00C00u;   // 2-bit index -> two digits of -2.0
 constexpr uint32_t kQueryPopDigits = 0x02777777u;  // 6.0 x 6, 1.0
 constexpr uint32_t kInvalidPopDigits = 0x00777777u;  // worth 6 * 36 = 216
+constexpr uint32_t kRecordBiasDw0 = 0x77777700u;  // six 6.0 digits in bytes 1..3
+constexpr uint32_t kRecordBiasDw1 = 0x00000200u;  // one 1.0 digit in byte 1
+constexpr int32_t kInvalidRowBias = 166;
 
 __device__ __forceinline__ void spread_f4(uint32_t c, uint32_t table, uint32_t *o) {
 #pragma unroll
@@ -46,8 +54,7 @@ __device__ __forceinline__ void spread_f4(uint32_t c, uint32_t table, uint32_t *
 // |r| = 6 * (v_0 + ... + v_5) + w as fp4 digits (v_i in {0, .5, 1, 1.5, 2, 3,
 // 4, 6}, w in {0, 1, 2}); 2 v_i taken greedily from {12, 8, 6, 4, 3, 2, 1}
 // covers every 3 m + w <= 166 within six digits.
-__device__ uint32_t pop_digits(uint32_t p) {
-  if (p > (uint32_t)kKeys) return kInvalidPopDigits;
+__device__ uint32_t six_one_digits(uint32_t p) {
   uint32_t m = p / 3, w = p % 3, pat = 0;
   const uint32_t two_v[7] = {12, 8, 6, 4, 3, 2, 1};
   const uint32_t code[7] = {0x7, 0x6, 0x5, 0x4, 0x3, 0x2, 0x1};
@@ -64,9 +71,23 @@ __device__ uint32_t pop_digits(uint32_t p) {
   return pat;
 }
 
+__device__ uint32_t pop_digits(uint32_t p) {
+  return p > (uint32_t)kKeys ? kInvalidPopDigits : six_one_digits(p);
+}
+
+// The bias B (|B| <= 167) as the same seven digits, each negated for B < 0.
+__device__ __forceinline__ uint32_t bias_digits(int32_t b) {
+  const uint32_t pat = six_one_digits((uint32_t)(b < 0 ? -b : b));
+  // the sign bit of every nonzero digit (fp4 e2m1: bit 3 of the nibble)
+  uint32_t neg = 0;
+#pragma unroll
+  for (int i = 0; i < 7; ++i) neg |= ((pat >> (4 * i)) & 0x7u) ? 0x8u << (4 * i) : 0u;
+  return b < 0 ? pat | neg : pat;
+}
+
 // Thread tid expands record tid of a 256-record stage: six 16-byte fragments
-// (keys of a lo, a hi, b lo, b hi, c, d) and the |r| digits in dword 3 of the
-// last one.
+// (keys of a lo, a hi, b lo, b hi, c, d), the |r| digits in dword 3 of the
+// last one and the record side of the bias digits in its dwords 0 and 1.
 __device__ __forceinline__ void expand_f4(const Rec1 &R, bool ok, uint8_t *buf,
                                           const uint32_t *poptab, uint32_t tid) {
   const uint64_t ra = ok ? R.a : 0, rb = ok ? R.b : 0;
@@ -78,6 +99,8 @@ __device__ __forceinline__ void expand_f4(const Rec1 &R, bool ok, uint8_t *buf,
   for (int f = 0; f < 6; ++f) spread_f4(ch[f], kDigitsRecord, dw + 4 * f);
   const uint32_t pr = (uint32_t)(__popcll(ra) + __popcll(rb) + __popc(rc) + __popc(rd));
   dw[23] = poptab[ok ? pr : 255u];
+  dw[20] |= kRecordBiasDw0;
+  dw[21] |= kRecordBiasDw1;
   v4i_ *dst = reinterpret_cast<v4i_ *>(buf + tid * kF4Stride);
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
@@ -86,19 +109,18 @@ __device__ __forceinline__ void expand_f4(const Rec1 &R, bool ok, uint8_t *buf,
   }
 }
 
-// A operands and accumulator init of a wave: lane holds query row
-// row0 + mq * 32 + (lane & 31) for the A fragments (K half lane >> 5), and for
-// the C input the rows of the 32x32 output layout.
+// A operands of a wave: lane holds query row row0 + mq * 32 + (lane & 31)
+// (K half lane >> 5), including the row's bias digits B = |q| - T - 1.
 template <int MQ>
 __device__ __forceinline__ void build_a_f4(const Workspace &ws, const QBlock &qb, uint32_t row0,
-                                           uint32_t lane, v8i (&A)[MQ][3], v16f (&C)[MQ]) {
+                                           uint32_t lane, v8i (&A)[MQ][3]) {
   const uint32_t h = lane >> 5;
 #pragma unroll
   for (int mq = 0; mq < MQ; ++mq) {
     const uint32_t row = row0 + mq * 32 + (lane & 31);
     uint64_t qa = 0, qbw = 0;
     uint32_t qcw = 0, qdw = 0;
-    float qc = 300.0f;
+    int32_t bias = kInvalidRowBias;
     const bool valid = row < qb.count;
     if (valid) {
       const uint32_t q = ws.perm[qb.first + row];
@@ -106,7 +128,7 @@ __device__ __forceinline__ void build_a_f4(const Workspace &ws, const QBlock &qb
       qbw = ws.qinfo[q].qb;
       qcw = ws.qinfo[q].qc;
       qdw = ws.qinfo[q].qd;
-      qc = (float)((int32_t)ws.qinfo[q].popc - (int32_t)ws.T[q] - 1);
+      bias = (int32_t)ws.qinfo[q].popc - (int32_t)ws.T[q] - 1;
     }
     const uint32_t ch[3] = {h ? (uint32_t)(qa >> 32) : (uint32_t)qa,
                             h ? (uint32_t)(qbw >> 32) : (uint32_t)qbw, h ? qdw : qcw};
@@ -114,14 +136,15 @@ __device__ __forceinline__ void build_a_f4(const Workspace &ws, const QBlock &qb
     for (int s = 0; s < 3; ++s) {
       uint32_t o[4];
       spread_f4(ch[s], kDigitsQuery, o);
-      if (s == 2 && h == 1) o[3] = valid ? kQueryPopDigits : 0u;
+      if (s == 2 && h == 1) {
+        const uint32_t bd = bias_digits(bias);
+        o[0] |= (bd & 0xFFFFFFu) << 8;  // against the record's six 6.0 digits
+        o[1] |= ((bd >> 24) & 0xFu) << 8;  // against its 1.0 digit
+        o[3] = valid ? kQueryPopDigits : 0u;
+      }
       v8i v = {(int)o[0], (int)o[1], (int)o[2], (int)o[3], 0, 0, 0, 0};
       A[mq][s] = v;
     }
-    // C input: element e of this lane is row 8 (e >> 2) + 4 h + (e & 3) of the tile
-#pragma unroll
-    for (int e = 0; e < 16; ++e)
-      C[mq][e] = __shfl(qc, (int)(8 * (e >> 2) + 4 * h + (e & 3)));
   }
 }
 
@@ -139,10 +162,11 @@ __device__ __forceinline__ void load_b_f4(const uint8_t *buf, int c, uint32_t la
 
 template <int MQ>
 __device__ __forceinline__ void multiply_f4(const v8i (&A)[MQ][3], const v8i (&B)[3],
-                                            const v16f (&C)[MQ], v16f (&acc)[MQ]) {
+                                            v16f (&acc)[MQ]) {
+  const v16f zero = {};  // the inline constant 0 as the C input
 #pragma unroll
   for (int mq = 0; mq < MQ; ++mq) {
-    acc[mq] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[mq][0], B[0], C[mq], 4, 4, 0, 127,
+    acc[mq] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[mq][0], B[0], zero, 4, 4, 0, 127,
                                                               0, 127);
     acc[mq] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[mq][1], B[1], acc[mq], 4, 4, 0,
                                                               127, 0, 127);
@@ -223,7 +247,7 @@ template <int MQ, bool COLS>
 __device__ __forceinline__ void stage_f4(const Workspace &ws, const QBlock &qb, const Stage &st,
                                          const uint8_t *buf, uint32_t row0, uint32_t lane,
                                          uint32_t wv, const v8i (&A)[MQ][3],
-                                         const v16f (&C)[MQ], HitBuf &hb) {
+                                         HitBuf &hb) {
   constexpr int kCols = kSubF4 / 32;
   if (COLS) {
 #pragma unroll
@@ -233,7 +257,7 @@ __device__ __forceinline__ void stage_f4(const Workspace &ws, const QBlock &qb, 
       v8i B[3];
       v16f acc[MQ];
       load_b_f4<MQ>(buf, c, lane, B);
-      multiply_f4<MQ>(A, B, C, acc);
+      multiply_f4<MQ>(A, B, acc);
       if (__builtin_expect(__ballot(or_bits<MQ>(acc) < 0) != 0, 0)) decode_f4<MQ>(ws, st, c, lane, acc, hb);
     }
     return;
@@ -245,15 +269,15 @@ __device__ __forceinline__ void stage_f4(const Workspace &ws, const QBlock &qb, 
   v8i B0[3], B1[3];
   v16f acc0[MQ], acc1[MQ];
   load_b_f4<MQ>(buf, 0, lane, B0);
-  multiply_f4<MQ>(A, B0, C, acc0);
+  multiply_f4<MQ>(A, B0, acc0);
   load_b_f4<MQ>(buf, 1, lane, B1);
 #pragma unroll 1
   for (int c = 0; c < kCols; c += 2) {
-    multiply_f4<MQ>(A, B1, C, acc1);  // block c + 1
+    multiply_f4<MQ>(A, B1, acc1);  // block c + 1
     if (c + 2 < kCols) load_b_f4<MQ>(buf, c + 2, lane, B0);
     if (__builtin_expect(__ballot(or_bits<MQ>(acc0) < 0) != 0, 0)) decode_f4<MQ>(ws, st, c, lane, acc0, hb);
     if (c + 2 < kCols) {
-      multiply_f4<MQ>(A, B0, C, acc0);  // block c + 2
+      multiply_f4<MQ>(A, B0, acc0);  // block c + 2
       load_b_f4<MQ>(buf, c + 3, lane, B1);
     }
     if (__builtin_expect(__ballot(or_bits<MQ>(acc1) < 0) != 0, 0)) decode_f4<MQ>(ws, st, c + 1, lane, acc1, hb);
@@ -283,7 +307,6 @@ __global__ __launch_bounds__(256, WPE) void k_scan_mfma_f4(Lib lib, Workspace ws
   const uint64_t nst = (it1 - it0) * kStagesF4;
   const uint32_t row0 = COLS ? 0u : wv * (MQ * 32);
   v8i A[MQ][3];
-  v16f C[MQ];
   uint32_t a_qb = 0xFFFFFFFFu;
   QBlock qb{};
   bool wave_live = false;
@@ -332,11 +355,11 @@ __global__ __launch_bounds__(256, WPE) void k_scan_mfma_f4(Lib lib, Workspace ws
           qb.rset = q->rset;
           qb.tiles = q->tiles;
           wave_live = qb.count > row0;
-          build_a_f4<MQ>(ws, qb, row0, lane, A, C);
+          build_a_f4<MQ>(ws, qb, row0, lane, A);
           hits_rows<kRows>(ws, qb, row0, lane, hb);
         }
         if (wave_live && cs.g1 > cs.g0)
-          stage_f4<MQ, COLS>(ws, qb, cs, lds[j & 1], row0, lane, wv, A, C, hb);
+          stage_f4<MQ, COLS>(ws, qb, cs, lds[j & 1], row0, lane, wv, A, hb);
         const int nx = (j + 1) % RING;  // a constant after unrolling
         const Stage cn = S[nx];
         expand_f4(R[nx], cn.g0 + tid < cn.g1, lds[(j + 1) & 1], poptab, tid);
