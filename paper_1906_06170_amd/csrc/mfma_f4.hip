@@ -362,10 +362,14 @@ __global__ __launch_bounds__(256, WPE) void k_scan_mfma_f4(Lib lib, Workspace ws
           stage_f4<MQ, COLS>(ws, qb, cs, lds[j & 1], row0, lane, wv, A, hb);
         const int nx = (j + 1) % RING;  // a constant after unrolling
         const Stage cn = S[nx];
+        // the expansion gates the block's barrier: it goes ahead of the
+        // products of the other waves on the SIMD
+        __builtin_amdgcn_s_setprio(2);
         expand_f4(R[nx], cn.g0 + tid < cn.g1, lds[(j + 1) & 1], poptab, tid);
         S[nx] = next_stage();
         R[nx] = load_rec1(lib, S[nx], tid);
         lds_barrier();
+        __builtin_amdgcn_s_setprio(0);
         cs = cn;
       }
     }
