@@ -494,6 +494,23 @@ void fps_make_blocks(Plan *P, uint32_t qbs, const std::vector<uint64_t> &tile_bo
     const uint32_t first = (uint32_t)P->perm.size();
     for (uint32_t i = 0; i < P->q; ++i)
       if (P->qinfo[i].rset == r && P->qinfo[i].keff > 0) P->perm.push_back(i);
+    // Every run of 32 rows samples the whole range of k: sorted by k, then laid
+    // out with stride W = ceil(n / 32) (sorted elements g, g + W, g + 2W, ...
+    // for g = 0, 1, ...).  A matrix-core wave decodes a result tile whenever
+    // any of its rows has a candidate, and a block's work items take as long
+    // as its busiest wave; queries arriving in runs of one k (a batch of
+    // concatenated requests) would otherwise gather the candidate-heavy
+    // large-k rows in a few blocks, whose items then set the grid's tail.
+    {
+      std::vector<uint32_t> sorted(P->perm.begin() + first, P->perm.end());
+      std::stable_sort(sorted.begin(), sorted.end(), [&](uint32_t x, uint32_t y) {
+        return P->qinfo[x].keff < P->qinfo[y].keff;
+      });
+      const size_t n = sorted.size(), W = (n + 31) / 32;
+      size_t o = first;
+      for (size_t g = 0; g < W; ++g)
+        for (size_t j = g; j < n; j += W) P->perm[o++] = sorted[j];
+    }
     const uint32_t cnt = (uint32_t)P->perm.size() - first;
     const RangeSet &rs = P->rsets[r];
     for (uint32_t f = 0; f < cnt; f += qbs) {
