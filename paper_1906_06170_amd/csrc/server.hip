@@ -3,9 +3,11 @@
 // The paper decouples the user side from the long computation with a queue
 // (Sections 3.1 and 4.4).  Here the queue feeds the GPU directly: requests are
 // admitted while the workspace pool has room for their candidate buffers,
-// coalesced first-come first-served into batches, and run on n_streams slots
+// coalesced first-come first-served into batches (capped by query count and,
+// optionally, by the earliest deadline; batcher.h), and run on n_streams slots
 // (one worker thread, one HIP stream and one workspace slice each), so a batch
-// can start while others are still on the device.  Each request keeps its own
+// can start while others are still on the device.  The last reserve_streams
+// slots run only under overload.  Each request keeps its own
 // k and stride mask inside the batch; batching never changes a result, since
 // every query of a batch is answered independently.
 #include <algorithm>
