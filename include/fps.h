@@ -306,7 +306,9 @@ fps_status fps_server_submit(fps_server *srv, const uint64_t *queries, uint32_t 
 fps_status fps_server_wait(fps_server *srv, uint64_t ticket, fps_hit *out, uint64_t out_capacity,
                            uint64_t *out_offset, fps_request_stats *stats);
 
-/* Latency and throughput counters since creation (or the last reset). */
+/* Latency and throughput counters since creation (or the last reset).  The
+ * counts cover every request; the latency percentiles and maximum cover the
+ * last 1,048,576 requests (a bounded window for long-running servers). */
 fps_status fps_server_stats_get(fps_server *srv, fps_server_stats *stats, int reset);
 
 /* Drains outstanding requests and releases the server (never the workspace). */

@@ -77,7 +77,10 @@ struct fps_server {
   bool stopping = false;
   fps::CostModel cost;  // service time of a batch (batcher.h)
   // statistics
+  // latencies of the last kLatWindow requests (a ring once full)
+  static constexpr size_t kLatWindow = size_t(1) << 20;
   std::vector<double> lat_us;
+  size_t lat_next = 0;
   uint64_t st_requests = 0, st_queries = 0, st_batches = 0, st_misses = 0, st_batch_q = 0;
 };
 
@@ -217,7 +220,12 @@ static void run_slot(fps_server *S, Slot *slot, bool reserve) {
         r->done = true;
         S->admitted_bytes -= r->bytes;
         const double us = (double)(t1 - r->submit_ns) / 1000.0;
-        S->lat_us.push_back(us);
+        if (S->lat_us.size() < fps_server::kLatWindow) {
+          S->lat_us.push_back(us);
+        } else {
+          S->lat_us[S->lat_next] = us;
+          S->lat_next = (S->lat_next + 1) % fps_server::kLatWindow;
+        }
         S->st_requests++;
         S->st_queries += r->q;
         if (r->deadline_us && us > (double)r->deadline_us) S->st_misses++;
@@ -370,6 +378,7 @@ extern "C" fps_status fps_server_stats_get(fps_server *srv, fps_server_stats *st
   }
   if (reset) {
     srv->lat_us.clear();
+    srv->lat_next = 0;
     srv->st_requests = srv->st_queries = srv->st_batches = srv->st_misses = srv->st_batch_q = 0;
   }
   return FPS_OK;
