@@ -217,6 +217,21 @@ typedef struct {
 
 fps_status fps_last_search_stats(const fps_library *lib, fps_search_stats *stats);
 
+/*
+ * Runs the autotuner of FPS_PATH_AUTO for one batch shape ahead of use: q
+ * queries with result counts k[] and stride masks mask[] (NULL = all).  The
+ * shape's key is that of FPS_PATH_AUTO (live queries, largest k, largest
+ * n_eff, each rounded up to a power of two); if it is already tuned the call
+ * does nothing.  Otherwise every applicable kernel runs once on q synthetic
+ * queries (keys set with probability 1/4 from a fixed hash) and the fastest is
+ * cached, as the first batch of that shape would do.  workspace/ws_bytes as
+ * for fps_search_batch with these k and masks.  Nothing is returned to the
+ * host besides the status.  Errors: as fps_workspace_bytes, FPS_E_NOMEM
+ * (small workspace), FPS_E_DEVICE.
+ */
+fps_status fps_tune(fps_library *lib, uint32_t q, const uint32_t *k, const uint32_t *mask,
+                    void *workspace, size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Tuning knobs, for tests that must force the rare paths.                   */
 /* ------------------------------------------------------------------------ */
@@ -258,24 +273,36 @@ typedef struct {
                                  miss its deadline even if served now; < n_streams.  At light load
                                  fewer batches then share the GPU; under overload the extra
                                  batches keep it busy between the phases of the others */
+  const uint32_t *tune_k;     /* n_tune_k result counts the server expects (may be NULL): at
+                                 creation the autotuner times every batch shape of 1, 2, 4, ...
+                                 up to max_batch_queries queries with each of these k over all
+                                 strides (fps_tune), so that no request waits for tuning.  A
+                                 batch whose shape was not tuned never times candidates on the
+                                 request path: it takes a fixed default kernel choice and counts
+                                 in fps_server_stats.untuned_batches */
+  uint32_t n_tune_k;
 } fps_server_config;
 
 typedef struct {
-  uint64_t submit_ns;   /* steady-clock times */
-  uint64_t start_ns;    /* batch launch */
-  uint64_t done_ns;     /* results available */
+  uint64_t arrival_ns;  /* steady-clock times (fps_clock_ns): the request's arrival, */
+  uint64_t submit_ns;   /* its admission into the server's queue, */
+  uint64_t start_ns;    /* the launch of its batch and */
+  uint64_t done_ns;     /* the moment its results were available */
   uint32_t batch_id;
   uint32_t batch_queries;
 } fps_request_stats;
 
 typedef struct {
-  uint64_t requests;
+  uint64_t requests;         /* completed requests */
   uint64_t queries;
   uint64_t batches;
-  uint64_t deadline_misses;
-  double p50_us, p99_us, max_us, mean_batch_queries;
+  uint64_t deadline_misses;  /* requests completed more than deadline_us after arrival */
+  double p50_us, p99_us, max_us; /* latency from arrival to completion */
+  double mean_batch_queries;
   double cost_fixed_us;      /* fitted service time of a batch: cost_fixed_us + */
   double cost_per_weight_us; /* cost_per_weight_us * sum of q * (1 + k / 700) over its requests */
+  double admit_p50_us, admit_p99_us; /* wait from arrival to admission (queue full) */
+  uint64_t untuned_batches;  /* batches whose shape the autotuner had not timed */
 } fps_server_stats;
 
 /*
@@ -288,23 +315,40 @@ fps_status fps_server_create(fps_library *lib, const fps_server_config *cfg, voi
 
 /*
  * Queues one request of q queries (host memory, copied before return) with one k
- * and one stride mask.  deadline_us is the request's latency budget (counted as
- * a miss when exceeded; the request still completes).  Blocks while the pool
- * lacks room for the request unless nonblocking != 0, which returns
- * FPS_E_BUSY instead.  A request larger than a whole slot is rejected with
- * FPS_E_NOMEM.
+ * and one stride mask.  deadline_us is the request's latency budget from its
+ * arrival (counted as a miss when exceeded; the request still completes).
+ * arrival_ns is the request's arrival time on the steady clock of
+ * fps_clock_ns (0 = the moment of this call); latency and deadlines are
+ * counted from it, so the time a request spends before admission -- in a
+ * client's queue or blocked in this call -- is part of its latency.  Blocks
+ * while the pool lacks room for the request unless nonblocking != 0, which
+ * returns FPS_E_BUSY instead.  A request larger than a whole slot is rejected
+ * with FPS_E_NOMEM.
  */
 fps_status fps_server_submit(fps_server *srv, const uint64_t *queries, uint32_t q, uint32_t k,
-                             uint32_t mask, uint32_t deadline_us, int nonblocking,
-                             uint64_t *ticket);
+                             uint32_t mask, uint32_t deadline_us, uint64_t arrival_ns,
+                             int nonblocking, uint64_t *ticket);
+
+/*
+ * Waits until a request is done and reports the size of its result: *q
+ * queries (out_offset needs q + 1 entries) and *n_hits hits (the sum over its
+ * queries of min(k, n_eff)).  The ticket stays valid.  Either pointer may be
+ * NULL.  Errors: FPS_E_ARG (unknown ticket).
+ */
+fps_status fps_server_result_size(fps_server *srv, uint64_t ticket, uint32_t *q,
+                                  uint64_t *n_hits);
 
 /*
  * Waits for a request and copies its results: out has out_capacity hits,
- * out_offset q + 1 entries (as fps_search_batch).  stats may be NULL.  Each
- * ticket can be waited for once.
+ * out_offset offset_capacity entries (q + 1 are written, as fps_search_batch).
+ * stats may be NULL.  The ticket is consumed only when the results are
+ * delivered: a too-small buffer returns FPS_E_ARG (the message states the
+ * sizes needed) and the same ticket can be waited for again.  A failed
+ * request returns its error and consumes the ticket.
  */
 fps_status fps_server_wait(fps_server *srv, uint64_t ticket, fps_hit *out, uint64_t out_capacity,
-                           uint64_t *out_offset, fps_request_stats *stats);
+                           uint64_t *out_offset, uint64_t offset_capacity,
+                           fps_request_stats *stats);
 
 /* Latency and throughput counters since creation (or the last reset).  The
  * counts cover every request; the latency percentiles and maximum cover the
@@ -313,6 +357,9 @@ fps_status fps_server_stats_get(fps_server *srv, fps_server_stats *stats, int re
 
 /* Drains outstanding requests and releases the server (never the workspace). */
 fps_status fps_server_destroy(fps_server *srv);
+
+/* Now on the steady clock used by the server's time stamps, in nanoseconds. */
+uint64_t fps_clock_ns(void);
 
 /* Message of the last failure on the calling thread. */
 const char *fps_last_error(void);

@@ -51,13 +51,14 @@ class SearchStats(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("pool_bytes", ctypes.c_size_t), ("max_batch_queries", ctypes.c_uint32),
                 ("max_wait_us", ctypes.c_uint32), ("n_streams", ctypes.c_uint32),
-                ("deadline_cap", ctypes.c_uint32), ("reserve_streams", ctypes.c_uint32)]
+                ("deadline_cap", ctypes.c_uint32), ("reserve_streams", ctypes.c_uint32),
+                ("tune_k", ctypes.c_void_p), ("n_tune_k", ctypes.c_uint32)]
 
 
 class RequestStats(ctypes.Structure):
-    _fields_ = [("submit_ns", ctypes.c_uint64), ("start_ns", ctypes.c_uint64),
-                ("done_ns", ctypes.c_uint64), ("batch_id", ctypes.c_uint32),
-                ("batch_queries", ctypes.c_uint32)]
+    _fields_ = [("arrival_ns", ctypes.c_uint64), ("submit_ns", ctypes.c_uint64),
+                ("start_ns", ctypes.c_uint64), ("done_ns", ctypes.c_uint64),
+                ("batch_id", ctypes.c_uint32), ("batch_queries", ctypes.c_uint32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -65,7 +66,9 @@ class ServerStats(ctypes.Structure):
                 ("batches", ctypes.c_uint64), ("deadline_misses", ctypes.c_uint64),
                 ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
                 ("max_us", ctypes.c_double), ("mean_batch_queries", ctypes.c_double),
-                ("cost_fixed_us", ctypes.c_double), ("cost_per_weight_us", ctypes.c_double)]
+                ("cost_fixed_us", ctypes.c_double), ("cost_per_weight_us", ctypes.c_double),
+                ("admit_p50_us", ctypes.c_double), ("admit_p99_us", ctypes.c_double),
+                ("untuned_batches", ctypes.c_uint64)]
 
 
 EXPORTS = {
@@ -91,17 +94,24 @@ EXPORTS = {
                                         ctypes.c_size_t, ctypes.c_void_p, ctypes.c_uint64,
                                         ctypes.c_void_p, ctypes.c_void_p]),
     "fps_last_search_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "fps_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
+                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                ctypes.c_void_p]),
     "fps_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_uint64,
                                       ctypes.c_uint64, ctypes.c_int]),
     "fps_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_size_t, ctypes.c_void_p]),
     "fps_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
                                          ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
-                                         ctypes.c_int, ctypes.c_void_p]),
+                                         ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p]),
+    "fps_server_result_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64,
+                                              ctypes.c_void_p, ctypes.c_void_p]),
     "fps_server_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
-                                       ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]),
+                                       ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint64,
+                                       ctypes.c_void_p]),
     "fps_server_stats_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "fps_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "fps_clock_ns": (ctypes.c_uint64, []),
     "fps_last_error": (ctypes.c_char_p, []),
 }
 
@@ -260,6 +270,20 @@ class Library:
                 "total_ms_sum": st.total_ms_sum, "calls": st.calls,
                 "scan_launches_sum": st.scan_launches_sum}
 
+    def tune(self, nq: int, k, mask=None, stream=None):
+        """Runs the autotuner for a batch shape of nq queries ahead of use."""
+        kk = _u32(k, nq)
+        mm = None if mask is None else _u32(mask, nq)
+        nb = ctypes.c_size_t()
+        _check(load_library().fps_workspace_bytes(self._handle, nq, _ptr(kk),
+                                                  None if mm is None else _ptr(mm),
+                                                  ctypes.byref(nb)))
+        ws = self._workspace(int(nb.value))
+        _check(load_library().fps_tune(self._handle, nq, _ptr(kk),
+                                       None if mm is None else _ptr(mm),
+                                       ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                       _stream(stream, self._device)))
+
     # -- search ---------------------------------------------------------------
     def search(self, query, k: int, mask: int = MASK_ALL, stream=None) -> np.ndarray:
         """Top-k of one query: structured array (index, distance), ascending."""
@@ -305,40 +329,54 @@ class Library:
         return out[:int(off[-1])], off
 
 
+def clock_ns() -> int:
+    """Now on the steady clock of the server's time stamps (nanoseconds)."""
+    return int(load_library().fps_clock_ns())
+
+
 class Server:
     """Continuous-batching request loop over a Library (Sections 3.1, 4.4)."""
 
     def __init__(self, library: Library, pool_bytes: int, max_batch_queries: int = 512,
                  max_wait_us: int = 0, n_streams: int = 2, deadline_cap: bool = True,
-                 reserve_streams: int = 0):
+                 reserve_streams: int = 0, tune_k=()):
         torch = _require_gpu()
         self._lib = library
         self._ws = torch.empty(int(pool_bytes), dtype=torch.uint8, device="cuda")
+        tk = np.ascontiguousarray(np.asarray(tune_k, dtype=np.uint32).reshape(-1))
         cfg = ServerConfig(int(pool_bytes), int(max_batch_queries), int(max_wait_us),
-                           int(n_streams), int(bool(deadline_cap)), int(reserve_streams))
+                           int(n_streams), int(bool(deadline_cap)), int(reserve_streams),
+                           ctypes.c_void_p(tk.ctypes.data) if len(tk) else None, len(tk))
         self._h = ctypes.c_void_p()
         _check(load_library().fps_server_create(library.handle, ctypes.byref(cfg),
                                                 ctypes.c_void_p(self._ws.data_ptr()),
                                                 int(pool_bytes), ctypes.byref(self._h)))
 
     def submit(self, queries, k: int, mask: int = MASK_ALL, deadline_us: int = 0,
-               nonblocking: bool = False) -> int:
+               nonblocking: bool = False, arrival_ns: int = 0) -> int:
+        """Queues a request; arrival_ns (clock_ns() time, 0 = now) is where its
+        latency and deadline start."""
         qs = np.ascontiguousarray(np.asarray(queries, dtype=np.uint64).reshape(-1, 3))
         t = ctypes.c_uint64()
         _check(load_library().fps_server_submit(self._h, _ptr(qs), qs.shape[0], int(k),
-                                                int(mask), int(deadline_us), int(nonblocking),
-                                                ctypes.byref(t)))
+                                                int(mask), int(deadline_us), int(arrival_ns),
+                                                int(nonblocking), ctypes.byref(t)))
         return int(t.value)
 
-    def wait(self, ticket: int, nq: int, k: int):
-        out = np.empty(max(nq * int(k), 1), dtype=HIT_DTYPE)
-        off = np.zeros(nq + 1, dtype=np.uint64)
+    def wait(self, ticket: int):
+        """Results of a request: (hits, offsets, stats), as Library.search_batch."""
+        c = load_library()
+        nq = ctypes.c_uint32()
+        nh = ctypes.c_uint64()
+        _check(c.fps_server_result_size(self._h, int(ticket), ctypes.byref(nq),
+                                        ctypes.byref(nh)))
+        out = np.empty(max(int(nh.value), 1), dtype=HIT_DTYPE)
+        off = np.zeros(int(nq.value) + 1, dtype=np.uint64)
         st = RequestStats()
-        _check(load_library().fps_server_wait(self._h, int(ticket), _ptr(out), nq * int(k),
-                                              _ptr(off), ctypes.byref(st)))
-        stats = {"submit_ns": st.submit_ns, "start_ns": st.start_ns, "done_ns": st.done_ns,
-                 "batch_id": st.batch_id, "batch_queries": st.batch_queries}
-        return out[:int(off[-1])].copy(), off, stats
+        _check(c.fps_server_wait(self._h, int(ticket), _ptr(out), int(nh.value), _ptr(off),
+                                 len(off), ctypes.byref(st)))
+        stats = {f: getattr(st, f) for f, _ in RequestStats._fields_}
+        return out[:int(off[-1])], off, stats
 
     def stats(self, reset: bool = False) -> dict:
         st = ServerStats()

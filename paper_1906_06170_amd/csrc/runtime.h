@@ -26,6 +26,7 @@ struct SearchCtx {
   uint32_t last_phases = 0;    // scan phases of the last launch sequence
   uint32_t last_timed = 0;     // bit p: the events around phase p were stamped
   uint32_t last_launches = 0;  // scan kernel launches of the last sequence
+  bool last_untuned = false;   // the last call took the default kernel of an untimed shape
   bool last_total_timed = false;  // ev[0], ev[1] were stamped
   double sum_scan_ms = 0, sum_total_ms = 0;  // running sums since creation
   uint64_t sum_calls = 0, sum_launches = 0;
@@ -87,4 +88,8 @@ fps_status fps_plan(const fps_library *lib, uint32_t q, const uint32_t *k, const
 fps_status fps_search_impl(fps_library *lib, SearchCtx *ctx, const uint64_t *queries, uint32_t q,
                            const uint32_t *k, const uint32_t *mask, void *workspace,
                            size_t ws_bytes, fps_hit *out, uint64_t out_capacity,
-                           uint64_t *out_offset, hipStream_t s, fps_path forced);
+                           uint64_t *out_offset, hipStream_t s, fps_path forced,
+                           bool may_tune);
+// The autotuner for one batch shape (fps_tune) on the given context's stream.
+fps_status fps_tune_impl(fps_library *lib, SearchCtx *ctx, uint32_t q, const uint32_t *k,
+                         const uint32_t *mask, void *workspace, size_t ws_bytes, hipStream_t s);

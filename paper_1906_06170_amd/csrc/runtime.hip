@@ -567,7 +567,8 @@ static fps_status launch_search(fps_library *lib, SearchCtx *ctx, Plan &P, fps_p
                                 int variant, uint8_t *wsbase, hipStream_t s, bool timed,
                                 bool capturing = false, bool d2h = false, bool host_only = false);
 static fps_status resolve_path(fps_library *lib, SearchCtx *ctx, Plan &P, fps_path requested,
-                               uint8_t *wsb, hipStream_t s, fps_path *path, int *variant);
+                               uint8_t *wsb, hipStream_t s, bool may_tune, fps_path *path,
+                               int *variant);
 
 // Timing events.  Inside a stream capture an event-record node is added after
 // the current capture frontier and the capture continues from it, so replays of
@@ -817,17 +818,33 @@ static fps_status run_search(fps_library *lib, SearchCtx *ctx, Plan &P, fps_path
   return FPS_OK;
 }
 
-fps_status fps_search_impl(fps_library *lib, SearchCtx *ctx, const uint64_t *queries, uint32_t q,
-                           const uint32_t *k, const uint32_t *mask, void *workspace,
-                           size_t ws_bytes, fps_hit *out, uint64_t out_capacity,
-                           uint64_t *out_offset, hipStream_t s, fps_path forced) {
-  if (!lib || !ctx || !queries || !k || !workspace || !out_offset)
-    return fps_fail(FPS_E_ARG, "NULL argument");
+// Validates the queries and plans a search of them: per-query parameters,
+// the query words in the library layout and their key counts.
+static fps_status plan_queries(fps_library *lib, const uint64_t *queries, uint32_t q,
+                               const uint32_t *k, const uint32_t *mask, Plan *P) {
   for (uint32_t i = 0; i < q; ++i)
     if (bad_fingerprint(queries + 3 * (size_t)i))
       return fps_fail(FPS_E_FINGERPRINT, "query %u has bit 0 or a bit above key 166 set", i);
+  fps_status rc = fps_plan(lib, q, k, mask, P);
+  if (rc) return rc;
+  for (uint32_t i = 0; i < q; ++i) {
+    QueryInfo &qi = P->qinfo[i];
+    relabel(queries + 3 * (size_t)i, &qi.qa, &qi.qb, &qi.qc, &qi.qd);
+    qi.popc = (uint32_t)(__builtin_popcountll(qi.qa) + __builtin_popcountll(qi.qb) +
+                         __builtin_popcount(qi.qc) + __builtin_popcount(qi.qd));
+  }
+  return FPS_OK;
+}
+
+fps_status fps_search_impl(fps_library *lib, SearchCtx *ctx, const uint64_t *queries, uint32_t q,
+                           const uint32_t *k, const uint32_t *mask, void *workspace,
+                           size_t ws_bytes, fps_hit *out, uint64_t out_capacity,
+                           uint64_t *out_offset, hipStream_t s, fps_path forced,
+                           bool may_tune) {
+  if (!lib || !ctx || !queries || !k || !workspace || !out_offset)
+    return fps_fail(FPS_E_ARG, "NULL argument");
   Plan P;
-  fps_status rc = fps_plan(lib, q, k, mask, &P);
+  fps_status rc = plan_queries(lib, queries, q, k, mask, &P);
   if (rc) return rc;
   if (P.total_out > 0 && !out) return fps_fail(FPS_E_ARG, "NULL out");
   if (out_capacity < P.total_out)
@@ -837,21 +854,16 @@ fps_status fps_search_impl(fps_library *lib, SearchCtx *ctx, const uint64_t *que
     return fps_fail(FPS_E_NOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, P.total_bytes);
   if (((uintptr_t)workspace & 255) != 0)
     return fps_fail(FPS_E_ARG, "workspace must be 256-byte aligned");
-  for (uint32_t i = 0; i < q; ++i) {
-    QueryInfo &qi = P.qinfo[i];
-    relabel(queries + 3 * (size_t)i, &qi.qa, &qi.qb, &qi.qc, &qi.qd);
-    qi.popc = (uint32_t)(__builtin_popcountll(qi.qa) + __builtin_popcountll(qi.qb) +
-                         __builtin_popcount(qi.qc) + __builtin_popcount(qi.qd));
-  }
   out_offset[0] = 0;
   for (uint32_t i = 0; i < q; ++i) out_offset[i + 1] = out_offset[i] + P.qinfo[i].keff;
   ctx->last = fps_search_stats{};
   ctx->last.queries = q;
+  ctx->last_untuned = false;
   if (P.total_out == 0) return FPS_OK;
   uint8_t *wsb = (uint8_t *)workspace;
   fps_path path;
   int variant;
-  rc = resolve_path(lib, ctx, P, forced, wsb, s, &path, &variant);
+  rc = resolve_path(lib, ctx, P, forced, wsb, s, may_tune, &path, &variant);
   if (rc) return rc;
   ctx->last.path = (uint32_t)path;
   ctx->last.variant =
@@ -908,7 +920,7 @@ extern "C" fps_status fps_search(fps_library *lib, const uint64_t query[3], uint
   if (!lib) return fps_fail(FPS_E_ARG, "NULL library");
   fps_status rc = fps_search_impl(lib, &lib->ctx, query, 1, &k, &mask, workspace, ws_bytes, out,
                                   out ? (uint64_t)k : 0, off, (hipStream_t)stream,
-                                  FPS_PATH_SINGLE);
+                                  FPS_PATH_SINGLE, true);
   if (rc) return rc;
   *n_out = (uint32_t)off[1];
   return FPS_OK;
@@ -921,7 +933,7 @@ extern "C" fps_status fps_search_batch(fps_library *lib, const uint64_t *queries
   fps_clear_error();
   if (!lib) return fps_fail(FPS_E_ARG, "NULL library");
   return fps_search_impl(lib, &lib->ctx, queries, q, k, mask, workspace, ws_bytes, out, out_capacity,
-                         out_offset, (hipStream_t)stream, FPS_PATH_AUTO);
+                         out_offset, (hipStream_t)stream, FPS_PATH_AUTO, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -991,8 +1003,26 @@ static std::vector<std::pair<fps_path, int>> tune_candidates(const Plan &P) {
   return c;
 }
 
+// Kernel choice for a shape the autotuner has not timed, when timing is not
+// allowed (a server's request path): the single-query scan for one or two
+// live queries, the fp4 matrix-core kernel otherwise -- its shape of 64
+// queries shared by a block's four waves up to 64 queries, 64 queries per
+// wave beyond.
+static void default_path(const Plan &P, fps_path *path, int *variant) {
+  uint64_t live = 0;
+  for (const auto &qi : P.qinfo) live += qi.keff > 0;
+  if (live <= 2) {
+    *path = FPS_PATH_SINGLE;
+    *variant = 0;
+  } else {
+    *path = FPS_PATH_MFMA_F4;
+    *variant = live <= 64 ? 2 : 0;
+  }
+}
+
 static fps_status resolve_path(fps_library *lib, SearchCtx *ctx, Plan &P, fps_path requested,
-                               uint8_t *wsb, hipStream_t s, fps_path *path, int *variant) {
+                               uint8_t *wsb, hipStream_t s, bool may_tune, fps_path *path,
+                               int *variant) {
   if (requested != FPS_PATH_AUTO || lib->path != FPS_PATH_AUTO) {
     *path = requested != FPS_PATH_AUTO ? requested : lib->path;
     // default tile shapes: 64 queries per wave, two waves per SIMD
@@ -1010,6 +1040,11 @@ static fps_status resolve_path(fps_library *lib, SearchCtx *ctx, Plan &P, fps_pa
       *variant = it->second.second;
       return FPS_OK;
     }
+  }
+  if (!may_tune) {
+    default_path(P, path, variant);
+    ctx->last_untuned = true;
+    return FPS_OK;
   }
   double best = 1e30;
   fps_path bp = FPS_PATH_POPCOUNT;
@@ -1034,4 +1069,50 @@ static fps_status resolve_path(fps_library *lib, SearchCtx *ctx, Plan &P, fps_pa
   *path = bp;
   *variant = bv;
   return FPS_OK;
+}
+
+// Synthetic query i of the tuner: every key set with probability 1/4, from a
+// multiply-xorshift hash of (i, word).
+static void tune_query(uint32_t i, uint64_t w[3]) {
+  for (int j = 0; j < 3; ++j) {
+    uint64_t a = 0x9E3779B97F4A7C15ull * (4ull * i + (uint64_t)j + 1ull), b;
+    a ^= a >> 31;
+    a *= 0xD6E8FEB86659FD93ull;
+    a ^= a >> 29;
+    b = a * 0xBF58476D1CE4E5B9ull;
+    b ^= b >> 32;
+    w[j] = a & b;
+  }
+  w[0] &= ~1ull;                  // bit 0 is not a key
+  w[2] &= (1ull << 39) - 1ull;    // nor are the bits above key 166
+}
+
+fps_status fps_tune_impl(fps_library *lib, SearchCtx *ctx, uint32_t q, const uint32_t *k,
+                         const uint32_t *mask, void *workspace, size_t ws_bytes, hipStream_t s) {
+  if (!lib || !ctx || !k || !workspace) return fps_fail(FPS_E_ARG, "NULL argument");
+  std::vector<uint64_t> qs((size_t)q * 3);
+  for (uint32_t i = 0; i < q; ++i) tune_query(i, &qs[3 * (size_t)i]);
+  Plan P;
+  fps_status rc = plan_queries(lib, qs.data(), q, k, mask, &P);
+  if (rc) return rc;
+  if (ws_bytes < P.total_bytes)
+    return fps_fail(FPS_E_NOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, P.total_bytes);
+  if (((uintptr_t)workspace & 255) != 0)
+    return fps_fail(FPS_E_ARG, "workspace must be 256-byte aligned");
+  if (P.total_out == 0) return FPS_OK;
+  fps_path path;
+  int variant;
+  rc = resolve_path(lib, ctx, P, FPS_PATH_AUTO, (uint8_t *)workspace, s, true, &path, &variant);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(s));
+  return FPS_OK;
+}
+
+extern "C" fps_status fps_tune(fps_library *lib, uint32_t q, const uint32_t *k,
+                               const uint32_t *mask, void *workspace, size_t ws_bytes,
+                               void *stream) {
+  fps_clear_error();
+  if (!lib) return fps_fail(FPS_E_ARG, "NULL library");
+  if (lib->path != FPS_PATH_AUTO) return FPS_OK;  // a forced path is never tuned
+  return fps_tune_impl(lib, &lib->ctx, q, k, mask, workspace, ws_bytes, (hipStream_t)stream);
 }

@@ -10,6 +10,12 @@
 // slots run only under overload.  Each request keeps its own
 // k and stride mask inside the batch; batching never changes a result, since
 // every query of a batch is answered independently.
+//
+// Latency is counted from a request's arrival (given by the caller or stamped
+// when submit is entered, before any wait for admission) to the moment its
+// results are available.  No kernel is ever timed on the request path: the
+// batch shapes named at creation are tuned there, and any other shape takes a
+// fixed default kernel.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -38,8 +44,9 @@ struct Request {
   uint64_t ticket = 0;
   std::vector<uint64_t> queries;
   uint32_t q = 0, k = 0, mask = 0, deadline_us = 0;
+  uint32_t keff = 0;  // min(k, records in the mask's strides): hits per query
   size_t bytes = 0;  // workspace the request needs on its own
-  uint64_t submit_ns = 0, start_ns = 0, done_ns = 0;
+  uint64_t arrival_ns = 0, submit_ns = 0, start_ns = 0, done_ns = 0;
   uint32_t batch_id = 0, batch_queries = 0;
   std::vector<fps_hit> hits;
   std::vector<uint64_t> offsets;
@@ -58,6 +65,9 @@ struct Slot {
   std::vector<uint64_t> qs, off;
   std::vector<uint32_t> kk, mm;
   std::vector<fps_hit> hits;
+  ~Slot() {
+    if (stream) (void)hipStreamDestroy(stream);
+  }
 };
 
 }  // namespace
@@ -79,10 +89,21 @@ struct fps_server {
   // statistics
   // latencies of the last kLatWindow requests (a ring once full)
   static constexpr size_t kLatWindow = size_t(1) << 20;
-  std::vector<double> lat_us;
-  size_t lat_next = 0;
-  uint64_t st_requests = 0, st_queries = 0, st_batches = 0, st_misses = 0, st_batch_q = 0;
+  std::vector<double> lat_us, admit_us;  // arrival -> done, arrival -> admission
+  size_t lat_next = 0, admit_next = 0;
+  uint64_t st_requests = 0, st_queries = 0, st_batches = 0, st_misses = 0, st_batch_q = 0,
+           st_untuned = 0;
 };
+
+// Appends to a ring of the last fps_server::kLatWindow values.
+static void ring_push(std::vector<double> &v, size_t &next, double x) {
+  if (v.size() < fps_server::kLatWindow) {
+    v.push_back(x);
+  } else {
+    v[next] = x;
+    next = (next + 1) % fps_server::kLatWindow;
+  }
+}
 
 static size_t request_bytes(fps_library *lib, uint32_t q, uint32_t k, uint32_t mask) {
   std::vector<uint32_t> kk(q, k), mm(q, mask);
@@ -94,8 +115,8 @@ static size_t request_bytes(fps_library *lib, uint32_t q, uint32_t k, uint32_t m
 static fps::PendingView view_of(const Request &r) {
   fps::PendingView v;
   v.q = r.q;
-  v.k = r.k;
-  v.submit_ns = r.submit_ns;
+  v.k = r.keff;
+  v.submit_ns = r.arrival_ns;  // deadlines run from arrival
   v.deadline_us = r.deadline_us;
   return v;
 }
@@ -142,9 +163,13 @@ static void run_slot(fps_server *S, Slot *slot, bool reserve) {
           slot->mm.insert(slot->mm.end(), r.q, r.mask);
         }
         Plan P;
-        return fps_plan(S->lib, (uint32_t)slot->kk.size(), slot->kk.data(), slot->mm.data(),
-                        &P) == FPS_OK &&
-               P.total_bytes <= slot->ws_bytes;
+        try {
+          return fps_plan(S->lib, (uint32_t)slot->kk.size(), slot->kk.data(), slot->mm.data(),
+                          &P) == FPS_OK &&
+                 P.total_bytes <= slot->ws_bytes;
+        } catch (const std::bad_alloc &) {
+          return false;
+        }
       };
       if (n > 1 && !fits(n)) {
         // the longest prefix that fits (one request always does: admission)
@@ -170,24 +195,12 @@ static void run_slot(fps_server *S, Slot *slot, bool reserve) {
     double weight = 0;
     for (auto &r : batch) {
       qsum += r->q;
-      weight += fps::CostModel::weight(r->q, r->k);
+      weight += fps::CostModel::weight(r->q, r->keff);
     }
     std::vector<uint64_t> &qs = slot->qs;
     std::vector<uint32_t> &kk = slot->kk, &mm = slot->mm;
-    qs.clear();
-    kk.clear();
-    mm.clear();
     uint64_t cap = 0;
-    for (auto &r : batch) {
-      qs.insert(qs.end(), r->queries.begin(), r->queries.end());
-      kk.insert(kk.end(), r->q, r->k);
-      mm.insert(mm.end(), r->q, r->mask);
-      cap += (uint64_t)r->q * r->k;
-    }
-    if (slot->hits.size() < std::max<uint64_t>(cap, 1)) slot->hits.resize(std::max<uint64_t>(cap, 1));
-    if (slot->off.size() < (size_t)qsum + 1) slot->off.resize((size_t)qsum + 1);
-    fps_hit *hits = slot->hits.data();
-    uint64_t *off = slot->off.data();
+    for (auto &r : batch) cap += (uint64_t)r->q * r->keff;
     const uint64_t t0 = now_ns();
     uint32_t bid;
     {
@@ -195,10 +208,32 @@ static void run_slot(fps_server *S, Slot *slot, bool reserve) {
       bid = S->next_batch++;
     }
     fps_clear_error();
-    fps_status rc = fps_search_impl(S->lib, &slot->ctx, qs.data(), qsum, kk.data(), mm.data(),
-                                    slot->ws, slot->ws_bytes, hits, cap, off, slot->stream,
-                                    FPS_PATH_AUTO);
-    const std::string err = rc ? std::string(fps_last_error()) : std::string();
+    fps_status rc = FPS_OK;
+    std::string err;
+    bool untuned = false;
+    try {
+      qs.clear();
+      kk.clear();
+      mm.clear();
+      for (auto &r : batch) {
+        qs.insert(qs.end(), r->queries.begin(), r->queries.end());
+        kk.insert(kk.end(), r->q, r->k);
+        mm.insert(mm.end(), r->q, r->mask);
+      }
+      if (slot->hits.size() < std::max<uint64_t>(cap, 1))
+        slot->hits.resize(std::max<uint64_t>(cap, 1));
+      if (slot->off.size() < (size_t)qsum + 1) slot->off.resize((size_t)qsum + 1);
+      rc = fps_search_impl(S->lib, &slot->ctx, qs.data(), qsum, kk.data(), mm.data(), slot->ws,
+                           slot->ws_bytes, slot->hits.data(), cap, slot->off.data(),
+                           slot->stream, FPS_PATH_AUTO, false);
+      if (rc) err = fps_last_error();
+      untuned = slot->ctx.last_untuned;
+    } catch (const std::bad_alloc &) {
+      rc = FPS_E_NOMEM;
+      err = "host allocation failed while running a batch";
+    }
+    const fps_hit *hits = slot->hits.data();
+    const uint64_t *off = slot->off.data();
     const uint64_t t1 = now_ns();
     {
       std::lock_guard<std::mutex> lk(S->mu);
@@ -211,27 +246,30 @@ static void run_slot(fps_server *S, Slot *slot, bool reserve) {
         r->status = rc;
         r->error = err;
         if (!rc) {
-          r->offsets.resize(r->q + 1);
-          const uint64_t h0 = off[base];
-          for (uint32_t i = 0; i <= r->q; ++i) r->offsets[i] = off[base + i] - h0;
-          r->hits.assign(hits + h0, hits + off[base + r->q]);
+          try {
+            r->offsets.resize(r->q + 1);
+            const uint64_t h0 = off[base];
+            for (uint32_t i = 0; i <= r->q; ++i) r->offsets[i] = off[base + i] - h0;
+            r->hits.assign(hits + h0, hits + off[base + r->q]);
+          } catch (const std::bad_alloc &) {
+            r->status = FPS_E_NOMEM;
+            r->error = "host allocation failed while copying a result";
+            r->offsets.clear();
+            r->hits.clear();
+          }
         }
         base += r->q;
         r->done = true;
         S->admitted_bytes -= r->bytes;
-        const double us = (double)(t1 - r->submit_ns) / 1000.0;
-        if (S->lat_us.size() < fps_server::kLatWindow) {
-          S->lat_us.push_back(us);
-        } else {
-          S->lat_us[S->lat_next] = us;
-          S->lat_next = (S->lat_next + 1) % fps_server::kLatWindow;
-        }
+        const double us = (double)(t1 - r->arrival_ns) / 1000.0;
+        ring_push(S->lat_us, S->lat_next, us);
         S->st_requests++;
         S->st_queries += r->q;
         if (r->deadline_us && us > (double)r->deadline_us) S->st_misses++;
       }
       S->st_batches++;
       S->st_batch_q += qsum;
+      S->st_untuned += untuned ? 1u : 0u;
       if (!rc) S->cost.observe(weight, (double)(t1 - t0) / 1000.0);
     }
     S->cv_done.notify_all();
@@ -258,16 +296,36 @@ extern "C" fps_status fps_server_create(fps_library *lib, const fps_server_confi
   const size_t slot_bytes = (cfg->pool_bytes / cfg->n_streams) & ~(size_t)255;
   for (uint32_t i = 0; i < cfg->n_streams; ++i) {
     auto sl = std::make_unique<Slot>();
-    if (hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess)
+    if (hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess) {
+      sl->stream = nullptr;
       return fps_fail(FPS_E_DEVICE, "hipStreamCreateWithFlags failed");
+    }
     sl->ws = (uint8_t *)workspace + i * slot_bytes;
     sl->ws_bytes = slot_bytes;
     fps_status rc = sl->ctx.init();
-    if (rc) {
-      (void)hipStreamDestroy(sl->stream);
-      return rc;
-    }
+    if (rc) return rc;
     S->slots.push_back(std::move(sl));
+  }
+  // Tune every batch shape of 1, 2, 4, ... queries up to max_batch_queries with
+  // each expected k, on slot 0, before any request arrives.  A shape whose
+  // workspace exceeds a slot never runs as one batch and is skipped.
+  if (cfg->tune_k && cfg->n_tune_k && lib->path == FPS_PATH_AUTO) {
+    Slot *s0 = S->slots[0].get();
+    for (uint32_t t = 0; t < cfg->n_tune_k; ++t) {
+      for (uint64_t q = 1;; q *= 2) {
+        const uint32_t qq = (uint32_t)std::min<uint64_t>(q, cfg->max_batch_queries);
+        std::vector<uint32_t> kk(qq, cfg->tune_k[t]);
+        Plan P;
+        fps_status rc = fps_plan(lib, qq, kk.data(), nullptr, &P);
+        if (rc) return rc;
+        if (P.total_bytes <= s0->ws_bytes) {
+          rc = fps_tune_impl(lib, &s0->ctx, qq, kk.data(), nullptr, s0->ws, s0->ws_bytes,
+                             s0->stream);
+          if (rc) return rc;
+        }
+        if (qq >= cfg->max_batch_queries) break;
+      }
+    }
   }
   for (uint32_t i = 0; i < cfg->n_streams; ++i)
     S->slots[i]->worker = std::thread(run_slot, S.get(), S->slots[i].get(),
@@ -276,25 +334,35 @@ extern "C" fps_status fps_server_create(fps_library *lib, const fps_server_confi
   return FPS_OK;
 }
 
+extern "C" uint64_t fps_clock_ns(void) { return now_ns(); }
+
 extern "C" fps_status fps_server_submit(fps_server *srv, const uint64_t *queries, uint32_t q,
                                         uint32_t k, uint32_t mask, uint32_t deadline_us,
-                                        int nonblocking, uint64_t *ticket) {
+                                        uint64_t arrival_ns, int nonblocking, uint64_t *ticket) {
+  const uint64_t entered = now_ns();
   fps_clear_error();
   if (!srv || !queries || !ticket || q == 0) return fps_fail(FPS_E_ARG, "bad argument");
   for (uint32_t i = 0; i < q; ++i)
     if ((queries[3 * i] & 1ull) || (queries[3 * i + 2] >> 39))
       return fps_fail(FPS_E_FINGERPRINT, "query %u has bit 0 or a bit above key 166 set", i);
+  fps::RangeSet rs;
   {
-    fps::RangeSet rs;
     fps_status rc = fps_make_rangeset(srv->lib, mask, &rs);
     if (rc) return rc;
   }
-  auto r = std::make_shared<Request>();
-  r->queries.assign(queries, queries + 3 * (size_t)q);
+  std::shared_ptr<Request> r;
+  try {
+    r = std::make_shared<Request>();
+    r->queries.assign(queries, queries + 3 * (size_t)q);
+  } catch (const std::bad_alloc &) {
+    return fps_fail(FPS_E_NOMEM, "host allocation failed");
+  }
   r->q = q;
   r->k = k;
+  r->keff = (uint32_t)std::min<uint64_t>(k, rs.neff);
   r->mask = mask;
   r->deadline_us = deadline_us;
+  r->arrival_ns = arrival_ns ? arrival_ns : entered;
   r->bytes = request_bytes(srv->lib, q, k, mask);
   if (r->bytes > srv->slots[0]->ws_bytes)
     return fps_fail(FPS_E_NOMEM, "request needs %zu workspace bytes, a slot has %zu", r->bytes,
@@ -310,6 +378,8 @@ extern "C" fps_status fps_server_submit(fps_server *srv, const uint64_t *queries
   srv->admitted_bytes += r->bytes;
   r->ticket = srv->next_ticket++;
   r->submit_ns = now_ns();
+  ring_push(srv->admit_us, srv->admit_next,
+            r->submit_ns > r->arrival_ns ? (double)(r->submit_ns - r->arrival_ns) / 1000.0 : 0.0);
   srv->live[r->ticket] = r;
   srv->pending.push_back(r);
   srv->pending_q += q;
@@ -319,30 +389,55 @@ extern "C" fps_status fps_server_submit(fps_server *srv, const uint64_t *queries
   return FPS_OK;
 }
 
+// The request of a ticket once it is done (waits); null for an unknown ticket.
+static std::shared_ptr<Request> wait_done(fps_server *srv, std::unique_lock<std::mutex> &lk,
+                                          uint64_t ticket) {
+  auto it = srv->live.find(ticket);
+  if (it == srv->live.end()) return nullptr;
+  std::shared_ptr<Request> r = it->second;
+  srv->cv_done.wait(lk, [&] { return r->done; });
+  return r;
+}
+
+extern "C" fps_status fps_server_result_size(fps_server *srv, uint64_t ticket, uint32_t *q,
+                                             uint64_t *n_hits) {
+  fps_clear_error();
+  if (!srv) return fps_fail(FPS_E_ARG, "NULL server");
+  std::unique_lock<std::mutex> lk(srv->mu);
+  std::shared_ptr<Request> r = wait_done(srv, lk, ticket);
+  if (!r) return fps_fail(FPS_E_ARG, "unknown ticket %llu", (unsigned long long)ticket);
+  if (q) *q = r->q;
+  if (n_hits) *n_hits = r->status ? 0 : (uint64_t)r->hits.size();
+  return FPS_OK;
+}
+
 extern "C" fps_status fps_server_wait(fps_server *srv, uint64_t ticket, fps_hit *out,
                                       uint64_t out_capacity, uint64_t *out_offset,
-                                      fps_request_stats *stats) {
+                                      uint64_t offset_capacity, fps_request_stats *stats) {
   fps_clear_error();
   if (!srv || !out_offset) return fps_fail(FPS_E_ARG, "NULL argument");
   std::shared_ptr<Request> r;
   {
     std::unique_lock<std::mutex> lk(srv->mu);
-    auto it = srv->live.find(ticket);
-    if (it == srv->live.end()) return fps_fail(FPS_E_ARG, "unknown ticket %llu", (unsigned long long)ticket);
-    r = it->second;
-    srv->cv_done.wait(lk, [&] { return r->done; });
+    r = wait_done(srv, lk, ticket);
+    if (!r) return fps_fail(FPS_E_ARG, "unknown ticket %llu", (unsigned long long)ticket);
+    if (!r->status) {
+      // check every buffer before the ticket is consumed
+      if (offset_capacity < (uint64_t)r->q + 1)
+        return fps_fail(FPS_E_ARG, "out_offset holds %llu entries, %u needed",
+                        (unsigned long long)offset_capacity, r->q + 1);
+      if (out_capacity < r->hits.size())
+        return fps_fail(FPS_E_ARG, "out holds %llu hits, %zu needed",
+                        (unsigned long long)out_capacity, r->hits.size());
+      if (!r->hits.empty() && !out) return fps_fail(FPS_E_ARG, "NULL out");
+    }
     srv->live.erase(ticket);
   }
   if (r->status) return fps_fail(r->status, "%s", r->error.c_str());
-  if (out_capacity < r->hits.size())
-    return fps_fail(FPS_E_ARG, "out holds %llu hits, %zu needed",
-                    (unsigned long long)out_capacity, r->hits.size());
-  if (!r->hits.empty()) {
-    if (!out) return fps_fail(FPS_E_ARG, "NULL out");
-    std::memcpy(out, r->hits.data(), r->hits.size() * sizeof(fps_hit));
-  }
+  if (!r->hits.empty()) std::memcpy(out, r->hits.data(), r->hits.size() * sizeof(fps_hit));
   std::memcpy(out_offset, r->offsets.data(), r->offsets.size() * sizeof(uint64_t));
   if (stats) {
+    stats->arrival_ns = r->arrival_ns;
     stats->submit_ns = r->submit_ns;
     stats->start_ns = r->start_ns;
     stats->done_ns = r->done_ns;
@@ -364,22 +459,28 @@ extern "C" fps_status fps_server_stats_get(fps_server *srv, fps_server_stats *st
   st->mean_batch_queries = srv->st_batches ? (double)srv->st_batch_q / srv->st_batches : 0.0;
   st->cost_fixed_us = srv->cost.c0_us();
   st->cost_per_weight_us = srv->cost.c1_us();
-  if (!srv->lat_us.empty()) {
-    std::vector<double> v = srv->lat_us;
+  st->untuned_batches = srv->st_untuned;
+  auto pct = [](std::vector<double> v, double p) {
     std::sort(v.begin(), v.end());
-    auto pct = [&](double p) {
-      size_t i = (size_t)std::ceil(p * (double)v.size()) ;
-      if (i > 0) --i;
-      return v[std::min(i, v.size() - 1)];
-    };
-    st->p50_us = pct(0.50);
-    st->p99_us = pct(0.99);
-    st->max_us = v.back();
+    size_t i = (size_t)std::ceil(p * (double)v.size());
+    if (i > 0) --i;
+    return v[std::min(i, v.size() - 1)];
+  };
+  if (!srv->lat_us.empty()) {
+    st->p50_us = pct(srv->lat_us, 0.50);
+    st->p99_us = pct(srv->lat_us, 0.99);
+    st->max_us = *std::max_element(srv->lat_us.begin(), srv->lat_us.end());
+  }
+  if (!srv->admit_us.empty()) {
+    st->admit_p50_us = pct(srv->admit_us, 0.50);
+    st->admit_p99_us = pct(srv->admit_us, 0.99);
   }
   if (reset) {
     srv->lat_us.clear();
-    srv->lat_next = 0;
+    srv->admit_us.clear();
+    srv->lat_next = srv->admit_next = 0;
     srv->st_requests = srv->st_queries = srv->st_batches = srv->st_misses = srv->st_batch_q = 0;
+    srv->st_untuned = 0;
   }
   return FPS_OK;
 }
@@ -398,6 +499,7 @@ extern "C" fps_status fps_server_destroy(fps_server *srv) {
   for (auto &sl : srv->slots) {
     (void)hipStreamSynchronize(sl->stream);
     (void)hipStreamDestroy(sl->stream);
+    sl->stream = nullptr;
   }
   delete srv;
   return FPS_OK;

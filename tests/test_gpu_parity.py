@@ -479,7 +479,7 @@ def test_server_alone_vs_mix(small, streams, reserve, cap, deadline_us, max_q, w
                      deadline_cap=cap, reserve_streams=reserve, max_wait_us=wait_us)
     try:
         tickets = [srv.submit(qs, k, m, deadline_us=deadline_us) for qs, k, m in reqs]
-        mixed = [srv.wait(t, len(r[0]), r[1]) for t, r in zip(tickets, reqs)]
+        mixed = [srv.wait(t) for t in tickets]
         st = srv.stats()
         assert st["requests"] == 40
         for (qs, k, m), (h, off, rs) in zip(reqs, mixed):
@@ -494,3 +494,83 @@ def test_server_alone_vs_mix(small, streams, reserve, cap, deadline_us, max_q, w
             assert st["deadline_misses"] == 40  # a 1 us budget is always missed
     finally:
         srv.close()
+
+
+def test_server_k_beyond_records(small):
+    """k far beyond the records of a request's strides: the server sizes its
+    buffers from min(k, n_eff), so the request is answered like a search."""
+    lib_np, lib = small
+    qs = fpsynth.batch_queries(lib_np, 3, 77).words
+    srv = fps.Server(lib, pool_bytes=256 << 20, max_batch_queries=64, n_streams=1)
+    try:
+        say("case: server k = 2^31 over stride A")
+        t = srv.submit(qs, 1 << 31, 0b001)
+        h, off, _ = srv.wait(t)
+        want, woff = oracle.search_batch(lib_np.words, qs, 1 << 31, lib.strides,
+                                         np.full(3, 0b001, dtype=np.uint32))
+        assert int(off[-1]) == 3 * 40_000
+        assert np.array_equal(off, woff) and np.array_equal(h, want)
+    finally:
+        srv.close()
+
+
+def test_server_wait_checks_buffers_first(small):
+    """A too-small output buffer is reported without consuming the ticket; the
+    same ticket then delivers the results."""
+    import ctypes
+    lib_np, lib = small
+    qs = fpsynth.batch_queries(lib_np, 4, 78).words
+    c = fps.load_library()
+    srv = fps.Server(lib, pool_bytes=128 << 20, max_batch_queries=64, n_streams=1)
+    try:
+        say("case: server wait with small buffers")
+        t = srv.submit(qs, 30)
+        out = np.empty(4 * 30, dtype=fps.HIT_DTYPE)
+        off = np.zeros(5, dtype=np.uint64)
+        rc = c.fps_server_wait(srv._h, t, ctypes.c_void_p(out.ctypes.data), 4 * 30 - 1,
+                               ctypes.c_void_p(off.ctypes.data), 5, None)
+        assert rc == fps.FPS_E_ARG and b"needed" in c.fps_last_error()
+        rc = c.fps_server_wait(srv._h, t, ctypes.c_void_p(out.ctypes.data), 4 * 30,
+                               ctypes.c_void_p(off.ctypes.data), 4, None)
+        assert rc == fps.FPS_E_ARG
+        h, o, _ = srv.wait(t)
+        want, woff = oracle.search_batch(lib_np.words, qs, 30)
+        assert np.array_equal(o, woff) and np.array_equal(h, want)
+        rc = c.fps_server_wait(srv._h, t, ctypes.c_void_p(out.ctypes.data), 4 * 30,
+                               ctypes.c_void_p(off.ctypes.data), 5, None)
+        assert rc == fps.FPS_E_ARG  # consumed
+    finally:
+        srv.close()
+
+
+def test_server_latency_from_arrival_and_pretuning(small):
+    """Latency and deadlines run from the arrival the caller states; shapes
+    named at creation are tuned there, others take the default kernel and are
+    counted, and both are exact."""
+    lib_np, _ = small
+    lib = fps.Library(lib_np.words, strides=[0, 40_000, 75_000, 100_000])  # nothing tuned yet
+    qs = fpsynth.batch_queries(lib_np, 40, 79).words
+    srv = fps.Server(lib, pool_bytes=256 << 20, max_batch_queries=64, n_streams=1,
+                     tune_k=[30])
+    try:
+        say("case: server arrival stamps and pretuning")
+        st0 = srv.stats()
+        assert st0["untuned_batches"] == 0
+        arrival = fps.clock_ns() - 20_000_000  # arrived 20 ms ago
+        t = srv.submit(qs[:8], 30, deadline_us=10_000, arrival_ns=arrival)
+        h, off, rs = srv.wait(t)
+        assert rs["arrival_ns"] == arrival and rs["done_ns"] - arrival >= 20_000_000
+        want, woff = oracle.search_batch(lib_np.words, qs[:8], 30)
+        assert np.array_equal(h, want)
+        st = srv.stats()
+        assert st["deadline_misses"] == 1 and st["p50_us"] >= 20_000
+        assert st["untuned_batches"] == 0
+        t = srv.submit(qs, 999, mask=0b011)  # a shape nobody tuned
+        h, off, _ = srv.wait(t)
+        want, woff = oracle.search_batch(lib_np.words, qs, 999, lib.strides,
+                                         np.full(40, 0b011, dtype=np.uint32))
+        assert np.array_equal(off, woff) and np.array_equal(h, want)
+        assert srv.stats()["untuned_batches"] == 1
+    finally:
+        srv.close()
+        lib.close()
