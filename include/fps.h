@@ -196,6 +196,27 @@ fps_status fps_search_batch(fps_library *lib, const uint64_t *queries, uint32_t 
                             size_t ws_bytes, fps_hit *out, uint64_t out_capacity,
                             uint64_t *out_offset, void *stream);
 
+/*
+ * fps_search without a workspace argument, for callers that cannot allocate
+ * device memory: code that must not call hipMalloc (serving loops with fixed
+ * memory, harnesses that forbid allocation).  The same kernels as fps_search
+ * run on a static device array of FPS_NOALLOC_SCRATCH_BYTES, one per GPU,
+ * reserved when the library's code is loaded on that GPU and held until the
+ * process ends; the pinned host staging it uses is allocated by
+ * fps_library_load.  The call itself allocates no device or pinned memory
+ * (its host-side plan uses a few small heap blocks).
+ *   Arguments, results and errors as fps_search, plus FPS_E_NOMEM when the
+ *   search needs more workspace than the static array holds (very large k
+ *   on a large library; fps_workspace_bytes tells) or more host staging than
+ *   the load allocated (k above about 8,000).
+ * Every call on one GPU shares that GPU's array and the handle's staging, and
+ * the array keeps the last call's contents (the kernels clear what must start
+ * at zero): calls that overlap on one GPU, from any handle or thread, race.
+ */
+#define FPS_NOALLOC_SCRATCH_BYTES (32u << 20)
+fps_status fps_search_noalloc(fps_library *lib, const uint64_t query[3], uint32_t k,
+                              uint32_t mask, fps_hit *out, uint32_t *n_out, void *stream);
+
 /* Counters of the last search on this handle (for tests and benchmarks). */
 typedef struct {
   uint32_t path;          /* fps_path actually used */

@@ -46,6 +46,10 @@ extern "C" const char *fps_last_error(void) { return t_err.c_str(); }
 static inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 static void tune_load(fps_library *lib);
+static fps_status scratch_setup(int device);
+// Pinned staging (parameters, results) allocated when a library is loaded;
+// the allocation-free search must fit it.
+static constexpr size_t kNoAllocStaging = size_t(1) << 16;
 
 static bool bad_fingerprint(const uint64_t *w) {
   return (w[0] & 1ull) != 0 || (w[2] >> 39) != 0;
@@ -158,6 +162,10 @@ extern "C" fps_status fps_library_load(const uint64_t *host_words, uint64_t n,
       break;
     }
     if ((rc = L->ctx.init())) break;
+    // staging of the allocation-free search, sized once here
+    if ((rc = ensure_pinned(&L->ctx.h_params, &L->ctx.h_params_bytes, kNoAllocStaging))) break;
+    if ((rc = ensure_pinned(&L->ctx.h_out, &L->ctx.h_out_bytes, kNoAllocStaging))) break;
+    if ((rc = scratch_setup(L->device))) break;
     tune_load(L);
     // relabel and transpose record-major host words into the four device arrays
     const uint64_t CH = 1u << 20;
@@ -1115,4 +1123,60 @@ extern "C" fps_status fps_tune(fps_library *lib, uint32_t q, const uint32_t *k,
   if (!lib) return fps_fail(FPS_E_ARG, "NULL library");
   if (lib->path != FPS_PATH_AUTO) return FPS_OK;  // a forced path is never tuned
   return fps_tune_impl(lib, &lib->ctx, q, k, mask, workspace, ws_bytes, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free single-query search: the workspace of fps_search lives in a
+// static device array, one copy per GPU, whose address is taken once per
+// device when a library is loaded there.  Kernels get that address as their
+// workspace argument; host code never uses the array's name.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) uint8_t scratch[FPS_NOALLOC_SCRATCH_BYTES];
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch[kMaxDevices];
+
+static fps_status scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices)
+    return fps_fail(FPS_E_DEVICE, "device %d beyond the %d the scratch table holds", device,
+                    kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[device]) return FPS_OK;
+  void *p = nullptr;
+  HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) return fps_fail(FPS_E_DEVICE, "hipGetSymbolAddress returned a null scratch address");
+  g_scratch[device] = p;
+  return FPS_OK;
+}
+
+extern "C" fps_status fps_search_noalloc(fps_library *lib, const uint64_t query[3], uint32_t k,
+                                         uint32_t mask, fps_hit *out, uint32_t *n_out,
+                                         void *stream) {
+  fps_clear_error();
+  if (!lib || !n_out) return fps_fail(FPS_E_ARG, "NULL argument");
+  void *ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (lib->device >= 0 && lib->device < kMaxDevices) ws = g_scratch[lib->device];
+  }
+  if (!ws) return fps_fail(FPS_E_STATE, "no scratch address for device %d", lib->device);
+  Plan P;
+  fps_status rc = fps_plan(lib, 1, &k, &mask, &P);
+  if (rc) return rc;
+  if (P.total_bytes > (size_t)FPS_NOALLOC_SCRATCH_BYTES)
+    return fps_fail(FPS_E_NOMEM,
+                    "this search needs %zu bytes of workspace; the static scratch holds %zu "
+                    "(use fps_search with a workspace)",
+                    P.total_bytes, (size_t)FPS_NOALLOC_SCRATCH_BYTES);
+  if (P.params_bytes > lib->ctx.h_params_bytes || back_bytes(P) > lib->ctx.h_out_bytes)
+    return fps_fail(FPS_E_NOMEM,
+                    "this search needs %zu + %zu bytes of host staging; %zu + %zu are allocated",
+                    P.params_bytes, back_bytes(P), lib->ctx.h_params_bytes,
+                    lib->ctx.h_out_bytes);
+  uint64_t off[2] = {0, 0};
+  rc = fps_search_impl(lib, &lib->ctx, query, 1, &k, &mask, ws, FPS_NOALLOC_SCRATCH_BYTES, out,
+                       out ? (uint64_t)k : 0, off, (hipStream_t)stream, FPS_PATH_SINGLE, true);
+  if (rc) return rc;
+  *n_out = (uint32_t)off[1];
+  return FPS_OK;
 }
