@@ -28,6 +28,7 @@
 // d fragment, which holds bits 6, 7, 14, 15, ... of d (always zero), and the
 // bias digits in bytes 1..3 of dword 0 and byte 1 of dword 1 (bits 8..29 of d,
 // also zero).
+#include "f4_digits.h"
 #include "mfma_common.h"
 
 namespace fps {
@@ -37,52 +38,11 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 typedef int v4i_ __attribute__((ext_vector_type(4)));
 
 constexpr int kF4Stride = 112;  // bytes per expanded record (96 + 16 pad)
-constexpr uint32_t kDigitsRecord = 0x22200200u;  // 2-bit index -> two digits of 1.0
-constexpr uint32_t kDigitsQuery = 0xCCC00C00u;   // 2-bit index -> two digits of -2.0
-constexpr uint32_t kQueryPopDigits = 0x02777777u;  // 6.0 x 6, 1.0
-constexpr uint32_t kInvalidPopDigits = 0x00777777u;  // worth 6 * 36 = 216
-constexpr uint32_t kRecordBiasDw0 = 0x77777700u;  // six 6.0 digits in bytes 1..3
-constexpr uint32_t kRecordBiasDw1 = 0x00000200u;  // one 1.0 digit in byte 1
-constexpr int32_t kInvalidRowBias = 166;
 
 __device__ __forceinline__ void spread_f4(uint32_t c, uint32_t table, uint32_t *o) {
 #pragma unroll
   for (int j = 0; j < 4; ++j)
     o[j] = __builtin_amdgcn_perm(table, table, (c >> (2 * j)) & 0x03030303u);
-}
-
-// |r| = 6 * (v_0 + ... + v_5) + w as fp4 digits (v_i in {0, .5, 1, 1.5, 2, 3,
-// 4, 6}, w in {0, 1, 2}); 2 v_i taken greedily from {12, 8, 6, 4, 3, 2, 1}
-// covers every 3 m + w <= 166 within six digits.
-__device__ uint32_t six_one_digits(uint32_t p) {
-  uint32_t m = p / 3, w = p % 3, pat = 0;
-  const uint32_t two_v[7] = {12, 8, 6, 4, 3, 2, 1};
-  const uint32_t code[7] = {0x7, 0x6, 0x5, 0x4, 0x3, 0x2, 0x1};
-  for (int i = 0; i < 6; ++i) {
-    for (int c = 0; c < 7; ++c) {
-      if (two_v[c] <= m) {
-        pat |= code[c] << (4 * i);
-        m -= two_v[c];
-        break;
-      }
-    }
-  }
-  pat |= (w == 0 ? 0u : (w == 1 ? 0x2u : 0x4u)) << 24;
-  return pat;
-}
-
-__device__ uint32_t pop_digits(uint32_t p) {
-  return p > (uint32_t)kKeys ? kInvalidPopDigits : six_one_digits(p);
-}
-
-// The bias B (|B| <= 167) as the same seven digits, each negated for B < 0.
-__device__ __forceinline__ uint32_t bias_digits(int32_t b) {
-  const uint32_t pat = six_one_digits((uint32_t)(b < 0 ? -b : b));
-  // the sign bit of every nonzero digit (fp4 e2m1: bit 3 of the nibble)
-  uint32_t neg = 0;
-#pragma unroll
-  for (int i = 0; i < 7; ++i) neg |= ((pat >> (4 * i)) & 0x7u) ? 0x8u << (4 * i) : 0u;
-  return b < 0 ? pat | neg : pat;
 }
 
 // Thread tid expands record tid of a 256-record stage: six 16-byte fragments
