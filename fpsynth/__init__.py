@@ -1,7 +1,8 @@
 """Seeded synthetic MACCS-166-shaped inputs shared by the oracle's tests and the
 GPU path's tests and benchmark.
 
-This module draws bits only: it contains no distance or ranking arithmetic.
+This module draws bits and formats them (the text forms of a library file and of
+a typed query): it contains no distance, ranking or parsing arithmetic.
 The paper searches the PubChem MACCS-166 library (Sections 4.1-4.2), which is
 not available; these generators stand in for it with the library size the
 paper reports (95,417,114 records, Section 2.2) and fingerprints of the same
@@ -55,6 +56,11 @@ def _load():
         lib.fpsynth_library.restype = i32
         lib.fpsynth_queries.argtypes = [u64, u64, vp, u64, vp, vp, i32, i32, vp, vp, vp]
         lib.fpsynth_queries.restype = i32
+        lib.fpsynth_text_size.argtypes = [vp, u64, i32, u64, i32, i32]
+        lib.fpsynth_text_size.restype = u64
+        lib.fpsynth_text_write.argtypes = [vp, vp, u64, i32, ctypes.c_char_p, u64, i32, i32,
+                                           vp, i32]
+        lib.fpsynth_text_write.restype = i32
         _lib = lib
     return _lib
 
@@ -190,3 +196,59 @@ def poisson_requests(rate: float, duration_s: float, seed: int, max_q: int = 64,
     sizes = rng.integers(1, max_q + 1, size=nreq)
     ks = rng.choice(np.array(k_choices, dtype=np.uint32), size=nreq)
     return t, sizes.astype(np.int64), ks.astype(np.uint32)
+
+
+# --------------------------------------------------------------------------
+# Text form of a library (the paper's library file: one line of MACCS text
+# and a PubChem CID per molecule; Abstract, Fig. 3 step 1) and of queries (the
+# bracketed 0/1 list typed into the search box, Fig. 1).
+# --------------------------------------------------------------------------
+CID_MODULUS = 2_147_483_647  # 2^31 - 1, a prime
+
+
+def make_cids(n: int, seed: int) -> np.ndarray:
+    """n distinct ids in [1, 2^31 - 1] in an order unrelated to the row order:
+    id_i = (a * i + b) mod (2^31 - 1) + 1 with a, b drawn from the seed (a != 0,
+    so the map is injective for n < 2^31 - 1)."""
+    if n >= CID_MODULUS:
+        raise ValueError("too many records for distinct ids")
+    rng = np.random.default_rng([seed, 0x636964])
+    a = np.uint64(rng.integers(1, CID_MODULUS))
+    b = np.uint64(rng.integers(0, CID_MODULUS))
+    i = np.arange(n, dtype=np.uint64)
+    return (a * i + b) % np.uint64(CID_MODULUS) + np.uint64(1)
+
+
+def library_text(words: np.ndarray, ids: np.ndarray, width: int = 167, sep: str = " ",
+                 crlf: bool = False, final_eol: bool = True,
+                 nthreads: int | None = None) -> np.ndarray:
+    """Text of a library, one line per record: "<id><sep><keys>" where <keys>
+    is 167 characters '0'/'1' for positions 0..166 (width 167; position 0 holds
+    no key and is '0') or 166 characters for keys 1..166 (width 166).  Returns
+    a uint8 array of the bytes."""
+    c = _load()
+    w = np.ascontiguousarray(words, dtype=np.uint64).reshape(-1, NWORDS)
+    ids = np.ascontiguousarray(ids, dtype=np.uint64)
+    n = w.shape[0]
+    if ids.shape != (n,):
+        raise ValueError("one id per record")
+    sb = sep.encode()
+    size = int(c.fpsynth_text_size(_ptr(ids), n, int(width), len(sb), int(crlf),
+                                   int(final_eol)))
+    out = np.empty(size, dtype=np.uint8)
+    rc = c.fpsynth_text_write(_ptr(w), _ptr(ids), n, int(width), sb, len(sb), int(crlf),
+                              int(final_eol), _ptr(out), nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("fpsynth_text_write rejected its arguments")
+    return out
+
+
+def query_text(words, width: int = 166, trailing_comma: bool = True, spaces: bool = False) -> str:
+    """A query as typed into the search box of Fig. 1: "[v,v,...,v,]" with one
+    0/1 value per key (keys 1..166 for width 166; positions 0..166 for width
+    167)."""
+    w = [int(x) for x in np.asarray(words, dtype=np.uint64).reshape(NWORDS)]
+    first = 0 if width == 167 else 1
+    vals = [str((w[j >> 6] >> (j & 63)) & 1) for j in range(first, NKEYS + 1)]
+    s = (", " if spaces else ",").join(vals)
+    return "[" + s + ("," if trailing_comma else "") + "]"

@@ -174,3 +174,104 @@ int fpsynth_queries(uint64_t seed, uint64_t nq, const uint64_t *lib, uint64_t n,
   }
   return 0;
 }
+
+/*
+ * Text form of a library: one line per record, "<id><sep><keys><eol>", the
+ * shape of the paper's library file (Abstract: one line of MACCS text per
+ * molecule; Fig. 3 step 1 reads molecules and their CIDs from it).
+ *   width 167: the key characters are positions 0..166 ('0' at position 0,
+ *              which holds no key), width 166: keys 1..166 only;
+ *   ids[i]:    decimal, no leading zeros;
+ *   sep:       any separator string (e.g. " ", "\t", ",");
+ *   eol:       "\n", or "\r\n" when crlf != 0; final_eol = 0 leaves the last
+ *              line unterminated.
+ * This only formats the bits and ids it is given.
+ */
+static int dec_len(uint64_t v) {
+  int l = 1;
+  while (v >= 10) {
+    v /= 10;
+    ++l;
+  }
+  return l;
+}
+
+static uint64_t line_len(uint64_t id, int width, size_t seplen, int crlf) {
+  return (uint64_t)dec_len(id) + seplen + (uint64_t)width + (crlf ? 2u : 1u);
+}
+
+uint64_t fpsynth_text_size(const uint64_t *ids, uint64_t n, int width, uint64_t seplen,
+                           int crlf, int final_eol) {
+  uint64_t total = 0;
+  for (uint64_t i = 0; i < n; ++i) total += line_len(ids[i], width, (size_t)seplen, crlf);
+  if (n && !final_eol) total -= crlf ? 2u : 1u;
+  return total;
+}
+
+typedef struct {
+  const uint64_t *words, *ids;
+  uint64_t begin, end, offset;
+  int width, crlf, final_eol;
+  const char *sep;
+  size_t seplen;
+  uint64_t n;
+  char *out;
+} text_job;
+
+static void *text_worker(void *arg) {
+  text_job *jb = (text_job *)arg;
+  char *p = jb->out + jb->offset;
+  const int first = jb->width == 167 ? 0 : 1;
+  for (uint64_t i = jb->begin; i < jb->end; ++i) {
+    char digits[24];
+    int nd = 0;
+    uint64_t v = jb->ids[i];
+    do {
+      digits[nd++] = (char)('0' + v % 10);
+      v /= 10;
+    } while (v);
+    while (nd) *p++ = digits[--nd];
+    memcpy(p, jb->sep, jb->seplen);
+    p += jb->seplen;
+    const uint64_t *rec = jb->words + 3 * i;
+    for (int j = first; j <= NKEYS; ++j) *p++ = (char)('0' + ((rec[j >> 6] >> (j & 63)) & 1u));
+    if (i + 1 < jb->n || jb->final_eol) {
+      if (jb->crlf) *p++ = '\r';
+      *p++ = '\n';
+    }
+  }
+  return NULL;
+}
+
+/* Writes the text of records [0, n) into out (fpsynth_text_size bytes).  Returns
+ * 0, or -1 on bad arguments. */
+int fpsynth_text_write(const uint64_t *words, const uint64_t *ids, uint64_t n, int width,
+                       const char *sep, uint64_t seplen, int crlf, int final_eol, char *out,
+                       int nthreads) {
+  if (!words || !ids || !sep || !out || (width != 166 && width != 167)) return -1;
+  if (nthreads < 1) nthreads = 1;
+  if (nthreads > 256) nthreads = 256;
+  pthread_t th[256];
+  text_job jobs[256];
+  uint64_t off = 0;
+  for (int t = 0; t < nthreads; ++t) {
+    text_job *jb = &jobs[t];
+    jb->words = words;
+    jb->ids = ids;
+    jb->begin = n * (uint64_t)t / (uint64_t)nthreads;
+    jb->end = n * (uint64_t)(t + 1) / (uint64_t)nthreads;
+    jb->offset = off;
+    jb->width = width;
+    jb->crlf = crlf;
+    jb->final_eol = final_eol;
+    jb->sep = sep;
+    jb->seplen = (size_t)seplen;
+    jb->n = n;
+    jb->out = out;
+    for (uint64_t i = jb->begin; i < jb->end; ++i) off += line_len(ids[i], width, seplen, crlf);
+  }
+  for (int t = 1; t < nthreads; ++t) pthread_create(&th[t], NULL, text_worker, &jobs[t]);
+  text_worker(&jobs[0]);
+  for (int t = 1; t < nthreads; ++t) pthread_join(th[t], NULL);
+  return 0;
+}

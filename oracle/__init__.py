@@ -6,9 +6,11 @@ headers, helpers or tables); both sides only take inputs from `fpsynth`.
 
 The arithmetic lives in `oracle.c` (plain C, no intrinsics): the Manhattan
 distance of Section 4.3 evaluated key by key, the top-N of Fig. 3 step 6 with
-ties ordered by ascending library index, and the stride split of Section 2.1
-with the combine-and-sort rule of Section 4.3.  This module is argument
-marshalling around it.
+ties ordered by ascending library index, the stride split of Section 2.1
+with the combine-and-sort rule of Section 4.3, and the line-by-line reader of
+the library file (Fig. 3 step 1).  This module is argument marshalling around
+it, plus the parser of the bracketed query list of Fig. 1 (Fig. 3 step 2),
+written here in plain Python.
 
 Every function here is pinned by `tests/test_oracle_pins.py` against
 independent facts: brute force with Python integer bit counts and set algebra,
@@ -76,6 +78,8 @@ class Oracle:
         lib.oracle_search.restype = ctypes.c_int64
         lib.oracle_search_batch.argtypes = [vp, vp, vp, vp, u32, vp, u64, vp, vp, vp, i32]
         lib.oracle_search_batch.restype = i32
+        lib.oracle_read_text.argtypes = [vp, u64, vp, vp, u64, vp, vp]
+        lib.oracle_read_text.restype = ctypes.c_int64
         self._lib = lib
 
     def distance(self, a, b) -> int:
@@ -140,6 +144,107 @@ class Oracle:
             raise MemoryError("oracle_search_batch ran out of memory")
         return out[:int(off[-1])].copy(), off
 
+    def read_text(self, text):
+        """Records of a library file (Fig. 3 step 1): (words (n, 3) uint64,
+        ids (n,) uint64).  Raises TextError(line, kind) on the first malformed
+        line (kinds in TEXT_ERRORS)."""
+        buf = _text_bytes(text)
+        cap = int(np.count_nonzero(buf == 10)) + 1
+        words = np.zeros((cap, 3), dtype=np.uint64)
+        ids = np.zeros(cap, dtype=np.uint64)
+        line = ctypes.c_uint64()
+        kind = ctypes.c_int()
+        got = self._lib.oracle_read_text(_p(buf), len(buf), _p(words), _p(ids), cap,
+                                         ctypes.byref(line), ctypes.byref(kind))
+        if got < 0:
+            raise TextError(int(line.value), int(kind.value))
+        return words[:got].copy(), ids[:got].copy()
+
+
+# Problems of a library-file line, in the order they are checked (oracle.c).
+TEXT_ERRORS = {1: "line too long", 2: "id missing or longer than 19 digits",
+               3: "no separator after the id", 4: "keys not 166 or 167 characters 0/1",
+               5: "position 0 set", 6: "characters after the keys"}
+
+
+class TextError(ValueError):
+    def __init__(self, line: int, kind: int):
+        super().__init__(f"line {line}: {TEXT_ERRORS.get(kind, kind)}")
+        self.line = line
+        self.kind = kind
+
+
+def _text_bytes(text) -> np.ndarray:
+    if isinstance(text, str):
+        text = text.encode()
+    if isinstance(text, (bytes, bytearray, memoryview)):
+        return np.frombuffer(bytes(text), dtype=np.uint8)
+    return np.ascontiguousarray(text, dtype=np.uint8).reshape(-1)
+
+
+def parse_query(s: str) -> np.ndarray:
+    """The target fingerprint as typed into the search box of Fig. 1 (Fig. 3
+    step 2): a bracketed, comma-separated list of 0/1 values, blanks allowed
+    around every token and one comma allowed before the closing bracket.  166
+    values are keys 1..166; 167 values are positions 0..166, of which position
+    0 holds no key and must be 0.  Returns the three words (key j at bit j & 63
+    of word j >> 6).  Raises ValueError naming the character position."""
+    i, n = 0, len(s)
+
+    def skip(i):
+        while i < n and s[i] in " \t\r\n":
+            i += 1
+        return i
+
+    i = skip(i)
+    if i >= n or s[i] != "[":
+        raise ValueError(f"position {i}: expected '['")
+    i += 1
+    vals = []
+    while True:
+        i = skip(i)
+        if i < n and s[i] == "]":
+            break
+        if i < n and s[i] in "01":
+            vals.append(int(s[i]))
+            i += 1
+        else:
+            raise ValueError(f"position {i}: expected 0 or 1")
+        i = skip(i)
+        if i < n and s[i] == ",":
+            i += 1
+        elif i < n and s[i] == "]":
+            break
+        else:
+            raise ValueError(f"position {i}: expected ',' or ']'")
+    i = skip(i + 1)
+    if i != n:
+        raise ValueError(f"position {i}: characters after ']'")
+    if len(vals) not in (166, 167):
+        raise ValueError(f"{len(vals)} values; 166 or 167 expected")
+    first = 1 if len(vals) == 166 else 0
+    if first == 0 and vals[0] != 0:
+        raise ValueError("position 0 holds no key and must be 0")
+    v = 0
+    for c, x in enumerate(vals):
+        if x:
+            v |= 1 << (first + c)
+    return np.array([(v >> (64 * w)) & ((1 << 64) - 1) for w in range(3)], dtype=np.uint64)
+
+
+def parse_queries(text: str) -> np.ndarray:
+    """One bracketed list per line (blank lines skipped): (q, 3) words.  Raises
+    ValueError naming the 1-based line."""
+    out = []
+    for no, line in enumerate(text.split("\n"), start=1):
+        if not line.strip():
+            continue
+        try:
+            out.append(parse_query(line))
+        except ValueError as e:
+            raise ValueError(f"line {no}: {e}") from None
+    return np.array(out, dtype=np.uint64).reshape(-1, 3)
+
 
 _default: Oracle | None = None
 
@@ -167,3 +272,7 @@ def search(lib_words, query, k: int, ranges=None, nthreads: int = 1) -> np.ndarr
 
 def search_batch(lib_words, queries, k, strides=None, masks=None, nthreads: int = 1):
     return default().search_batch(lib_words, queries, k, strides, masks, nthreads)
+
+
+def read_text(text):
+    return default().read_text(text)

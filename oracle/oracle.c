@@ -187,3 +187,86 @@ int oracle_search_batch(const uint64_t *lib, const uint64_t *begin, const uint64
   }
   return 0;
 }
+
+/*
+ * The library file F of Fig. 3 step 1 ("obtain all the molecules from F,
+ * construct CID, matrix A"), read line by line as the paper's engine does
+ * (Abstract: one line of MACCS text per molecule).  The paper does not print
+ * the line format; the reading taken is
+ *     <id> <separator> <keys> [trailing blanks] <end of line>
+ *   id:        1..19 decimal digits (the PubChem CID);
+ *   separator: one or more of ' ', '\t', ',';
+ *   keys:      167 characters '0'/'1' for positions 0..166 (position 0 holds
+ *              no key and must be '0'), or 166 characters for keys 1..166;
+ *   blanks:    ' ', '\t', '\r' only;
+ *   a line has at most 255 characters before its '\n'; the last line may
+ *   lack the '\n'; a '\n' that ends the text starts no further line.
+ * Checks, in this order, name the first problem of a line:
+ *   1 line too long, 2 id missing or longer than 19 digits, 3 no separator,
+ *   4 keys not 166 or 167 characters '0'/'1', 5 position 0 set, 6 other
+ *   characters after the keys.
+ * Returns the number of records (lines) read, or -1 when a line is malformed
+ * (*err_line = its 1-based number, *err_kind = the problem) or more than cap
+ * records are present (*err_kind = 0).
+ */
+#define ORACLE_LINE_MAX 255
+
+static int is_digit(char c) { return c >= '0' && c <= '9'; }
+static int is_sep(char c) { return c == ' ' || c == '\t' || c == ','; }
+static int is_blank(char c) { return c == ' ' || c == '\t' || c == '\r'; }
+
+static int read_line(const char *s, uint64_t len, uint64_t rec[3], uint64_t *id) {
+  if (len > ORACLE_LINE_MAX) return 1;
+  uint64_t p = 0;
+  uint64_t v = 0;
+  while (p < len && is_digit(s[p])) {
+    if (p < 19) v = v * 10 + (uint64_t)(s[p] - '0');
+    ++p;
+  }
+  if (p == 0 || p > 19) return 2;
+  uint64_t q = p;
+  while (q < len && is_sep(s[q])) ++q;
+  if (q == p) return 3;
+  uint64_t r = q;
+  while (r < len && (s[r] == '0' || s[r] == '1')) ++r;
+  uint64_t width = r - q;
+  if (width != 166 && width != 167) return 4;
+  /* character c of the key field is key c (167 wide) or key c + 1 (166 wide) */
+  uint64_t first_key = (width == 167) ? 0 : 1;
+  rec[0] = rec[1] = rec[2] = 0;
+  for (uint64_t c = 0; c < width; ++c) {
+    uint64_t j = first_key + c;
+    if (s[q + c] == '1') {
+      if (j == 0) return 5;
+      rec[j >> 6] |= 1ull << (j & 63);
+    }
+  }
+  for (uint64_t t = r; t < len; ++t)
+    if (!is_blank(s[t])) return 6;
+  *id = v;
+  return 0;
+}
+
+int64_t oracle_read_text(const char *text, uint64_t len, uint64_t *words, uint64_t *ids,
+                         uint64_t cap, uint64_t *err_line, int *err_kind) {
+  uint64_t n = 0, pos = 0;
+  *err_line = 0;
+  *err_kind = 0;
+  while (pos < len) {
+    uint64_t end = pos;
+    while (end < len && text[end] != '\n') ++end;
+    if (n == cap) {
+      *err_line = n + 1;
+      return -1;
+    }
+    int kind = read_line(text + pos, end - pos, words + 3 * n, ids + n);
+    if (kind) {
+      *err_line = n + 1;
+      *err_kind = kind;
+      return -1;
+    }
+    ++n;
+    pos = end + 1; /* past the '\n' (or past the end of the text) */
+  }
+  return (int64_t)n;
+}

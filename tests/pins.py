@@ -274,9 +274,116 @@ def pin_batch_equals_single(orc):
         assert np.array_equal(hits[int(off[i]):int(off[i + 1])], one), i
 
 
+# ---------------- the library file and the query box (Fig. 3 steps 1-2, Fig. 1) ----------------
+def key_line(ident: str, keys, width: int = 167, sep: str = " ", tail: str = "") -> str:
+    """One library-file line written character by character from a key set."""
+    first = 0 if width == 167 else 1
+    return ident + sep + "".join("1" if j in keys else "0" for j in range(first, 167)) + tail
+
+
+def pin_text_handwritten(orc):
+    rnd = random.Random(17)
+    cases = [set(), {1}, {166}, {63, 64}, {127, 128}, {159, 160, 161}, set(KEYS),
+             {2, 3, 5, 7, 11, 13, 101, 163}]
+    cases += [set(rnd.sample(list(KEYS), rnd.randint(0, 166))) for _ in range(24)]
+    idents = ["1", "0007", "9999999999999999999", "11050016", "42"]
+    seps = [" ", "\t", ",", "  ", " ,\t"]
+    tails = ["", "\r", "  ", "\t\r"]
+    lines, want_keys, want_ids = [], [], []
+    for i, keys in enumerate(cases):
+        ident = idents[i % len(idents)]
+        lines.append(key_line(ident, keys, 167 if i % 3 else 166, seps[i % len(seps)],
+                              tails[i % len(tails)]))
+        want_keys.append(keys)
+        want_ids.append(int(ident))
+    for final in ("\n", ""):
+        words, ids = orc.read_text("\n".join(lines) + final)
+        assert len(words) == len(cases)
+        for i in range(len(cases)):
+            assert key_set(words[i]) == want_keys[i], i
+            assert as_int(words[i]) & 1 == 0
+            assert int(ids[i]) == want_ids[i], i
+
+
+def pin_text_errors(orc):
+    good = key_line("5", {3, 70})
+    bad = {
+        1: key_line("5", {3}, tail=" " * 100),
+        2: "",
+        3: key_line("5", {3}, sep="x"),
+        4: key_line("5", {3})[:100] + "2" + key_line("5", {3})[101:],
+        5: key_line("5", {0, 3}),
+        6: key_line("5", {3}, tail=" #"),
+    }
+    extra = {2: ["   " + key_line("5", {1}), key_line("1" * 20, {1}), "\r"],
+             4: [key_line("5", {1}) + "0", key_line("5", {1}, width=166)[:-1]]}
+    for kind, line in bad.items():
+        for b in [line] + extra.get(kind, []):
+            for at in (1, 4):
+                text = "\n".join([good] * (at - 1) + [b] + [good] * 3) + "\n"
+                try:
+                    orc.read_text(text)
+                except ValueError as e:
+                    assert (e.line, e.kind) == (at, kind), (kind, at, e.line, e.kind)
+                else:
+                    raise AssertionError(f"malformed line of kind {kind} accepted")
+    # the first malformed line is the one reported
+    text = "\n".join([good, bad[6], good, bad[3]])
+    try:
+        orc.read_text(text)
+    except ValueError as e:
+        assert (e.line, e.kind) == (2, 6)
+    else:
+        raise AssertionError("malformed text accepted")
+    # a final newline starts no record; the 255-character limit is inclusive
+    w, _ = orc.read_text(good + "\n")
+    assert len(w) == 1
+    w, _ = orc.read_text(key_line("5", {3}, tail=" " * (255 - len(key_line("5", {3})))))
+    assert len(w) == 1
+
+
+def pin_text_roundtrip(orc):
+    lib = fpsynth.make_library(20_000, 71)
+    ids = fpsynth.make_cids(20_000, 3)
+    for width, sep, crlf, final in ((167, " ", False, True), (166, "\t", True, True),
+                                    (167, ",", False, False), (166, "  ", True, False)):
+        text = fpsynth.library_text(lib.words, ids, width=width, sep=sep, crlf=crlf,
+                                    final_eol=final)
+        w, i = orc.read_text(text)
+        assert np.array_equal(w, lib.words), (width, sep, crlf, final)
+        assert np.array_equal(i, ids)
+
+
+def pin_query_list(orc):
+    import oracle
+    zeros = "[" + ",".join(["0"] * 166) + ",]"  # the box of Fig. 1, trailing comma
+    assert as_int(oracle.parse_query(zeros)) == 0
+    rnd = random.Random(23)
+    for t in range(40):
+        keys = set(rnd.sample(list(KEYS), rnd.randint(0, 166)))
+        width = 166 if t % 2 else 167
+        first = 0 if width == 167 else 1
+        vals = ["1" if j in keys else "0" for j in range(first, 167)]
+        sep = [",", ", ", " ,", "\t,\t"][t % 4]
+        s = " [" + sep.join(vals) + ("," if t % 3 == 0 else "") + "] "
+        assert key_set(oracle.parse_query(s)) == keys, t
+    for bad in ("", "[]", "[" + ",".join(["0"] * 165) + "]", "[" + ",".join(["0"] * 168) + "]",
+                "[" + ",".join(["0"] * 165 + ["2"]) + "]", "[" + ",".join(["0"] * 166),
+                "[" + ",".join(["0"] * 166) + "] x", "[1" + ",0" * 166 + "]",
+                "[" + ",,".join(["0"] * 166) + "]", "(" + ",".join(["0"] * 166) + ")"):
+        try:
+            oracle.parse_query(bad)
+        except ValueError:
+            continue
+        raise AssertionError(f"accepted {bad[:30]!r}")
+    many = oracle.parse_queries("\n" + zeros + "\n\n" + zeros.replace("0,]", "1]") + "\n")
+    assert many.shape == (2, 3) and key_set(many[1]) == {166}
+
+
 ALL_PINS = [
     pin_set_algebra, pin_special_cases, pin_bitcount_identities, pin_metric_axioms,
     pin_paper_broadcast_distances, pin_paper_broadcast_topk, pin_histogram_invariant,
     pin_planted_distances, pin_fig2_column, pin_chunked_equals_serial, pin_strides_merge,
     pin_k_edges, pin_identical_rows, pin_batch_equals_single,
+    pin_text_handwritten, pin_text_errors, pin_text_roundtrip, pin_query_list,
 ]

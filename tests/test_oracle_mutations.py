@@ -25,6 +25,12 @@ MUTATIONS = {
                           "for (int j = 1; j < njobs; ++j)\n      for"),
     "range_end_skipped": ("for (uint64_t i = begin[r]; i < end[r]; ++i)\n      topk_offer",
                           "for (uint64_t i = begin[r]; i + 1 < end[r]; ++i)\n      topk_offer"),
+    # the library-file reader (Fig. 3 step 1)
+    "text_key_offset": ("uint64_t first_key = (width == 167) ? 0 : 1;", "uint64_t first_key = 1;"),
+    "text_long_ids": ("if (p == 0 || p > 19) return 2;", "if (p == 0) return 2;"),
+    "text_tail_unchecked": ("if (!is_blank(s[t])) return 6;", "if (s[t] == 0) return 6;"),
+    "text_no_cr": ("c == ' ' || c == '\\t' || c == '\\r'; }", "c == ' ' || c == '\\t'; }"),
+    "text_key0_unchecked": ("if (j == 0) return 5;", "if (j == 0) j = 0;"),
 }
 
 RUNNER = r"""
