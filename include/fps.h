@@ -148,6 +148,97 @@ fps_status fps_set_timing(fps_library *lib, int enable);
 fps_status fps_set_variant(fps_library *lib, int variant);
 
 /* ------------------------------------------------------------------------ */
+/* The library file and the query box (Fig. 3 steps 1, 2 and 5; Fig. 1).     */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * The library file F of Fig. 3 step 1 holds one line of MACCS text per molecule
+ * (Abstract) and the molecule's PubChem CID, which the results carry (Fig. 3
+ * step 5, Fig. 2).  The paper prints no line format; these calls read
+ *     <id> <separator> <keys> [blanks] '\n'
+ *   id:        1..19 decimal digits (any 64-bit id up to 10^19 - 1);
+ *   separator: one or more of ' ', '\t', ',';
+ *   keys:      167 characters '0'/'1' for positions 0..166, of which position
+ *              0 holds no key and must be '0', or 166 characters for keys
+ *              1..166 (the two forms may be mixed);
+ *   blanks:    ' ', '\t', '\r' (so CRLF line ends are accepted);
+ *   a line has at most 255 characters before its '\n'; the last line may lack
+ *   its '\n'; a '\n' ending the text starts no line, any other empty line is
+ *   malformed.  Record i of the library is line i + 1 of the text.
+ * The text is parsed on the GPU from device memory: the caller copies the
+ * file's bytes into HBM (a torch tensor) first.
+ */
+
+/* Device workspace bytes for fps_text_count and fps_text_library_load on a text
+ * of text_bytes bytes (about 12 bytes per 16 KiB of text). Errors: FPS_E_ARG. */
+fps_status fps_text_workspace_bytes(uint64_t text_bytes, size_t *bytes);
+
+/*
+ * Number of records (lines) of a library text, so the caller can size the
+ * library buffer (fps_library_device_bytes) and the id column.
+ *   text:       device memory, text_bytes > 0 bytes, 16-byte aligned.
+ *   workspace:  device memory of ws_bytes >= fps_text_workspace_bytes, 256-byte
+ *               aligned; its contents are scratch.
+ *   stream:     hipStream_t; the call returns when the count is known.
+ * Lines are not validated here (fps_text_library_load does that).
+ * Errors: FPS_E_ARG (NULL, empty or misaligned text), FPS_E_NOMEM (small
+ * workspace), FPS_E_DEVICE.
+ */
+fps_status fps_text_count(const void *text, uint64_t text_bytes, void *workspace,
+                          size_t ws_bytes, void *stream, uint64_t *n_records);
+
+/*
+ * Builds a library from its text on the GPU (Fig. 3 step 1: the molecules of F
+ * become the matrix A and the CID column).
+ *   text, text_bytes, workspace, ws_bytes, stream: as fps_text_count.
+ *   n_records:    the count fps_text_count returned (checked again here).
+ *   stride_begin, nstrides, device_buf, device_bytes, out: as fps_library_load.
+ *   ids_device:   device memory for n_records uint64 ids (record i's id at
+ *                 [i]), or NULL to discard the ids;
+ *   ids_host:     host memory for n_records uint64 ids, or NULL.  When given
+ *                 (it needs ids_device), the ids are copied there and the
+ *                 handle keeps the pointer for fps_hit_ids: it must stay valid
+ *                 until fps_library_free.
+ * Every line is validated; the first malformed line is reported by number:
+ * FPS_E_ARG "line L: <problem>" (problems: line too long, id missing or
+ * longer than 19 digits, no separator, keys not 166 or 167 characters '0'/'1',
+ * characters other than blanks after the keys), or FPS_E_FINGERPRINT for a
+ * 167-character key field with position 0 set.  Also FPS_E_ARG (n_records
+ * differs from the text's line count, and the errors of fps_library_load),
+ * FPS_E_NOMEM, FPS_E_DEVICE.  The text and the workspace are not kept.
+ */
+fps_status fps_text_library_load(const void *text, uint64_t text_bytes, uint64_t n_records,
+                                 const uint64_t *stride_begin, uint32_t nstrides, void *workspace,
+                                 size_t ws_bytes, void *device_buf, size_t device_bytes,
+                                 uint64_t *ids_device, uint64_t *ids_host, void *stream,
+                                 fps_library **out);
+
+/* Fig. 3 step 5 ("CID + K"): ids[i] = the id of record hits[i].index, from the
+ * id table of a library loaded from text with ids_host.  Host only.
+ * Errors: FPS_E_ARG (NULL, an index beyond the library), FPS_E_STATE (the
+ * library has no id table). */
+fps_status fps_hit_ids(const fps_library *lib, const fps_hit *hits, uint64_t n, uint64_t *ids);
+
+/*
+ * The target as typed into the search box of Fig. 1 (Fig. 3 step 2: the target
+ * fingerprint becomes the vector b): "[v,v,...,v]", each v '0' or '1', blanks
+ * around any token, one optional ',' before ']' (Fig. 1 shows one).  166 values
+ * are keys 1..166; 167 values are positions 0..166 (position 0 must be 0).
+ *   text/len: host memory (not NUL-terminated necessarily).
+ *   query:    receives the three words (key j at bit j & 63 of word j >> 6).
+ * Errors: FPS_E_ARG with the character position, FPS_E_FINGERPRINT (position
+ * 0 set).  Host only; no device work.
+ */
+fps_status fps_parse_query(const char *text, size_t len, uint64_t query[3]);
+
+/* A batch of targets, one bracketed list per line; lines holding only blanks
+ * are skipped.  queries: room for capacity x 3 words; *nq receives the count.
+ * Errors as fps_parse_query, the message naming the 1-based line; FPS_E_ARG
+ * when more than capacity lists are present. */
+fps_status fps_parse_queries(const char *text, size_t len, uint64_t *queries, uint32_t capacity,
+                             uint32_t *nq);
+
+/* ------------------------------------------------------------------------ */
 /* Search (Fig. 3 steps 2-6; single and batch searches of Section 4.4).       */
 /* ------------------------------------------------------------------------ */
 

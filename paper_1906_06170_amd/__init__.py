@@ -115,6 +115,19 @@ EXPORTS = {
     "fps_server_stats_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "fps_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "fps_clock_ns": (ctypes.c_uint64, []),
+    "fps_text_workspace_bytes": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_void_p]),
+    "fps_text_count": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                      ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]),
+    "fps_text_library_load": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64,
+                                             ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
+                                             ctypes.c_size_t, ctypes.c_void_p, ctypes.c_size_t,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p]),
+    "fps_hit_ids": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                   ctypes.c_void_p]),
+    "fps_parse_query": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "fps_parse_queries": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t, ctypes.c_void_p,
+                                         ctypes.c_uint32, ctypes.c_void_p]),
     "fps_last_error": (ctypes.c_char_p, []),
 }
 
@@ -179,29 +192,99 @@ def _u32(a, n, default=None) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.uint32)
 
 
-class Library:
-    """A fingerprint library resident in HBM (Fig. 3 step 1)."""
+ID_HIT_DTYPE = np.dtype([("id", np.uint64), ("distance", np.uint32)])
 
-    def __init__(self, words: np.ndarray, strides=None, stream=None):
+
+def parse_query(text: str) -> np.ndarray:
+    """The target as typed into the search box of Fig. 1 ("[0,1,...,0,]"):
+    the three fingerprint words (fps_parse_query)."""
+    b = text.encode() if isinstance(text, str) else bytes(text)
+    out = np.zeros(3, dtype=np.uint64)
+    _check(load_library().fps_parse_query(b, len(b), _ptr(out)))
+    return out
+
+
+def parse_queries(text: str) -> np.ndarray:
+    """One bracketed list per line (blank lines skipped): (q, 3) words."""
+    b = text.encode() if isinstance(text, str) else bytes(text)
+    cap = b.count(b"\n") + 1
+    out = np.zeros((cap, 3), dtype=np.uint64)
+    nq = ctypes.c_uint32()
+    _check(load_library().fps_parse_queries(b, len(b), _ptr(out), cap, ctypes.byref(nq)))
+    return out[:nq.value].copy()
+
+
+class Library:
+    """A fingerprint library resident in HBM (Fig. 3 step 1).
+
+    Library(words) uploads (n, 3) fingerprint words; Library(text=...) parses a
+    library file (bytes, a uint8 array, or a uint8 torch tensor already on the
+    GPU) on the GPU and keeps its id column (Library.ids)."""
+
+    def __init__(self, words: np.ndarray | None = None, strides=None, stream=None, *,
+                 text=None):
         torch = _require_gpu()
         c = load_library()
+        self._ws = None
+        self._ws_sizes = {}
+        self._handle = ctypes.c_void_p()
+        self.ids = None
+        self.text_stats = None
+        if (words is None) == (text is None):
+            raise ValueError("give either words or text")
+        if text is not None:
+            self._load_text(torch, c, text, strides, stream)
+            return
         w = np.ascontiguousarray(words, dtype=np.uint64).reshape(-1, 3)
         self.n = int(w.shape[0])
         nbytes = int(c.fps_library_device_bytes(self.n))
         self._buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         self._device = self._buf.device.index
-        self._ws = None
-        self._ws_sizes = {}
-        self._handle = ctypes.c_void_p()
-        if strides is None:
-            st, ns = None, 0
-        else:
-            st = np.ascontiguousarray(strides, dtype=np.uint64)
-            ns = len(st) - 1
-        self.strides = [0, self.n] if strides is None else [int(x) for x in strides]
+        st, ns = self._stride_table(strides)
         _check(c.fps_library_load(_ptr(w), self.n, None if st is None else _ptr(st), ns,
                                   ctypes.c_void_p(self._buf.data_ptr()), nbytes, _stream(stream),
                                   ctypes.byref(self._handle)))
+
+    def _stride_table(self, strides):
+        self.strides = [0, self.n] if strides is None else [int(x) for x in strides]
+        if strides is None:
+            return None, 0
+        st = np.ascontiguousarray(strides, dtype=np.uint64)
+        return st, len(st) - 1
+
+    def _load_text(self, torch, c, text, strides, stream):
+        if isinstance(text, torch.Tensor):
+            dtext = text if text.is_cuda else text.to("cuda")
+        else:
+            if isinstance(text, (bytes, bytearray, memoryview)):
+                text = np.frombuffer(bytes(text), dtype=np.uint8)
+            text = np.ascontiguousarray(text, dtype=np.uint8).reshape(-1)
+            if not text.flags.writeable:
+                text = text.copy()
+            dtext = torch.from_numpy(text).to("cuda")
+        dtext = dtext.contiguous()
+        nt = int(dtext.numel())
+        wsb = ctypes.c_size_t()
+        _check(c.fps_text_workspace_bytes(nt, ctypes.byref(wsb)))
+        tws = torch.empty(max(int(wsb.value), 256), dtype=torch.uint8, device="cuda")
+        n = ctypes.c_uint64()
+        s = _stream(stream)
+        _check(c.fps_text_count(ctypes.c_void_p(dtext.data_ptr()), nt,
+                                ctypes.c_void_p(tws.data_ptr()), tws.numel(), s,
+                                ctypes.byref(n)))
+        self.n = int(n.value)
+        nbytes = int(c.fps_library_device_bytes(self.n))
+        self._buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self._device = self._buf.device.index
+        self._ids_dev = torch.empty(max(self.n, 1), dtype=torch.int64, device="cuda")
+        self.ids = np.empty(max(self.n, 1), dtype=np.uint64)
+        st, ns = self._stride_table(strides)
+        _check(c.fps_text_library_load(
+            ctypes.c_void_p(dtext.data_ptr()), nt, self.n, None if st is None else _ptr(st), ns,
+            ctypes.c_void_p(tws.data_ptr()), tws.numel(), ctypes.c_void_p(self._buf.data_ptr()),
+            nbytes, ctypes.c_void_p(self._ids_dev.data_ptr()), _ptr(self.ids), s,
+            ctypes.byref(self._handle)))
+        self.ids = self.ids[:self.n]
 
     # -- helpers --------------------------------------------------------------
     @property
@@ -214,6 +297,7 @@ class Library:
             self._handle = ctypes.c_void_p()
         self._buf = None
         self._ws = None
+        self._ids_dev = None
 
     def __del__(self):
         try:
@@ -307,6 +391,24 @@ class Library:
                                          ctypes.c_void_p(ws.data_ptr()), ws.numel(), _ptr(out),
                                          ctypes.byref(nout), _stream(stream, self._device)))
         return out[:nout.value].copy()
+
+    def hit_ids(self, hits: np.ndarray) -> np.ndarray:
+        """Fig. 3 step 5: the id of every hit's record (libraries loaded from text)."""
+        h = np.ascontiguousarray(hits, dtype=HIT_DTYPE)
+        out = np.empty(max(len(h), 1), dtype=np.uint64)
+        _check(load_library().fps_hit_ids(self._handle, _ptr(h), len(h), _ptr(out)))
+        return out[:len(h)].copy()
+
+    def search_ids(self, query, k: int, mask: int = MASK_ALL, stream=None) -> np.ndarray:
+        """Top-k of one query as (id, distance) pairs, ascending (Fig. 2); the
+        query may be given as the typed bracketed list of Fig. 1."""
+        if isinstance(query, (str, bytes)):
+            query = parse_query(query)
+        h = self.search(query, k, mask, stream)
+        out = np.empty(len(h), dtype=ID_HIT_DTYPE)
+        out["id"] = self.hit_ids(h)
+        out["distance"] = h["distance"]
+        return out
 
     def search_batch(self, queries, k, mask=None, stream=None):
         """Independent top-k per query.  Returns (hits, offsets): query i's hits

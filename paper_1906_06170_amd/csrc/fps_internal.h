@@ -103,6 +103,21 @@ struct Workspace {
   uint32_t *fb_bin_total; // fallback: kBins
 };
 
+// Library-layout words of a fingerprint given as three words with key j at bit
+// (j & 63) of word (j >> 6): key 160 moves into the always-zero bit 0 of a, keys
+// 161..166 go to d.
+__host__ __device__ inline void relabel3(uint64_t w0, uint64_t w1, uint64_t w2, uint64_t *a,
+                                         uint64_t *b, uint32_t *c, uint32_t *d) {
+  *a = w0 | ((w2 >> 32) & 1ull);
+  *b = w1;
+  *c = (uint32_t)w2;
+  *d = (uint32_t)((w2 >> 33) & 0x3Full);
+}
+
+inline void relabel(const uint64_t *w, uint64_t *a, uint64_t *b, uint32_t *c, uint32_t *d) {
+  relabel3(w[0], w[1], w[2], a, b, c, d);
+}
+
 struct Lib {
   const uint64_t *a, *b;
   const uint32_t *c;

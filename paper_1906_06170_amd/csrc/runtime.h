@@ -62,6 +62,7 @@ struct fps_library {
   bool timing = false;  // HIP events around the kernels of every call
   bool graphs = true;  // capture and replay repeated launch shapes
   SearchCtx ctx;  // staging of direct calls on this handle
+  const uint64_t *ids = nullptr;  // caller-owned host id of every record (text loads), or null
   std::mutex tune_mu;
   std::map<TuneKey, std::pair<fps_path, int>> tuned;
 };
@@ -81,6 +82,12 @@ struct Plan {
 };
 
 fps_status fps_fail(fps_status s, const char *fmt, ...);
+// A handle over caller-owned device memory for n records (strides validated,
+// device queried, staging allocated); the records themselves are not written.
+fps_status fps_library_new(uint64_t n, const uint64_t *stride_begin, uint32_t nstrides,
+                           void *device_buf, size_t device_bytes, fps_library **out);
+// Zeroes the padding records [n, np) of a new handle's arrays on stream s.
+fps_status fps_library_zero_tail(fps_library *lib, hipStream_t s);
 void fps_clear_error();
 fps_status fps_make_rangeset(const fps_library *lib, uint32_t mask, fps::RangeSet *rs);
 fps_status fps_plan(const fps_library *lib, uint32_t q, const uint32_t *k, const uint32_t *mask,

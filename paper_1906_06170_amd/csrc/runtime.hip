@@ -79,16 +79,6 @@ extern "C" size_t fps_library_device_bytes(uint64_t n) {
   return (size_t)(np * kBytesPerRecord);
 }
 
-// Library-layout words of a fingerprint given as three words with key j at bit
-// (j & 63) of word (j >> 6): key 160 moves into the always-zero bit 0 of a, keys
-// 161..166 go to d (see fps_internal.h).
-static inline void relabel(const uint64_t *w, uint64_t *a, uint64_t *b, uint32_t *c,
-                           uint32_t *d) {
-  *a = w[0] | ((w[2] >> 32) & 1ull);
-  *b = w[1];
-  *c = (uint32_t)w[2];
-  *d = (uint32_t)((w[2] >> 33) & 0x3Full);
-}
 
 static Lib lib_view(const fps_library *lib) {
   Lib L;
@@ -117,12 +107,9 @@ fps_status SearchCtx::init() {
   return FPS_OK;
 }
 
-extern "C" fps_status fps_library_load(const uint64_t *host_words, uint64_t n,
-                                       const uint64_t *stride_begin, uint32_t nstrides,
-                                       void *device_buf, size_t device_bytes, void *stream,
-                                       fps_library **out) {
-  fps_clear_error();
-  if (!host_words || !device_buf || !out) return fps_fail(FPS_E_ARG, "NULL argument");
+fps_status fps_library_new(uint64_t n, const uint64_t *stride_begin, uint32_t nstrides,
+                           void *device_buf, size_t device_bytes, fps_library **out) {
+  if (!device_buf || !out) return fps_fail(FPS_E_ARG, "NULL argument");
   if (n == 0 || n >= (1ull << 32)) return fps_fail(FPS_E_ARG, "n = %llu out of range", (unsigned long long)n);
   if (device_bytes < fps_library_device_bytes(n))
     return fps_fail(FPS_E_ARG, "device buffer of %zu bytes < %zu needed", device_bytes,
@@ -141,10 +128,6 @@ extern "C" fps_status fps_library_load(const uint64_t *host_words, uint64_t n,
     for (uint32_t s = 0; s < nstrides; ++s)
       if (st[s + 1] < st[s]) return fps_fail(FPS_E_ARG, "stride offsets must not decrease");
   }
-  for (uint64_t i = 0; i < n; ++i)
-    if (bad_fingerprint(host_words + 3 * i))
-      return fps_fail(FPS_E_FINGERPRINT, "record %llu has bit 0 or a bit above key 166 set",
-                      (unsigned long long)i);
   auto *L = new (std::nothrow) fps_library();
   if (!L) return fps_fail(FPS_E_NOMEM, "host allocation failed");
   L->n = n;
@@ -152,7 +135,6 @@ extern "C" fps_status fps_library_load(const uint64_t *host_words, uint64_t n,
   L->nstrides = (uint32_t)st.size() - 1;
   std::copy(st.begin(), st.end(), L->strides);
   L->dev = (uint64_t *)device_buf;
-  hipStream_t s = (hipStream_t)stream;
   fps_status rc = FPS_OK;
   do {
     if (hipGetDevice(&L->device) != hipSuccess ||
@@ -167,6 +149,45 @@ extern "C" fps_status fps_library_load(const uint64_t *host_words, uint64_t n,
     if ((rc = ensure_pinned(&L->ctx.h_out, &L->ctx.h_out_bytes, kNoAllocStaging))) break;
     if ((rc = scratch_setup(L->device))) break;
     tune_load(L);
+  } while (0);
+  if (rc) {
+    delete L;
+    return rc;
+  }
+  *out = L;
+  return FPS_OK;
+}
+
+// Zeroes the records [n, np) of every array (they are scanned but never reported).
+fps_status fps_library_zero_tail(fps_library *L, hipStream_t s) {
+  uint8_t *da = (uint8_t *)L->dev, *db = da + 8 * L->np, *dc = db + 8 * L->np,
+          *dd = dc + 4 * L->np;
+  const uint64_t n = L->n, tail = L->np - n;
+  if (tail &&
+      (hipMemsetAsync(da + 8 * n, 0, 8 * tail, s) != hipSuccess ||
+       hipMemsetAsync(db + 8 * n, 0, 8 * tail, s) != hipSuccess ||
+       hipMemsetAsync(dc + 4 * n, 0, 4 * tail, s) != hipSuccess ||
+       hipMemsetAsync(dd + n, 0, tail, s) != hipSuccess))
+    return fps_fail(FPS_E_DEVICE, "hipMemsetAsync failed");
+  return FPS_OK;
+}
+
+extern "C" fps_status fps_library_load(const uint64_t *host_words, uint64_t n,
+                                       const uint64_t *stride_begin, uint32_t nstrides,
+                                       void *device_buf, size_t device_bytes, void *stream,
+                                       fps_library **out) {
+  fps_clear_error();
+  if (!host_words || !device_buf || !out) return fps_fail(FPS_E_ARG, "NULL argument");
+  if (n < (1ull << 32))
+    for (uint64_t i = 0; i < n; ++i)
+      if (bad_fingerprint(host_words + 3 * i))
+        return fps_fail(FPS_E_FINGERPRINT, "record %llu has bit 0 or a bit above key 166 set",
+                        (unsigned long long)i);
+  fps_library *L = nullptr;
+  fps_status rc = fps_library_new(n, stride_begin, nstrides, device_buf, device_bytes, &L);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  do {
     // relabel and transpose record-major host words into the four device arrays
     const uint64_t CH = 1u << 20;
     void *pin = nullptr;
@@ -195,13 +216,7 @@ extern "C" fps_status fps_library_load(const uint64_t *host_words, uint64_t n,
           hipMemcpyAsync(dd + c0, sd, m, hipMemcpyHostToDevice, s) != hipSuccess)
         rc = fps_fail(FPS_E_DEVICE, "upload failed");
     }
-    const uint64_t tail = L->np - n;
-    if (!rc && tail &&
-        (hipMemsetAsync(da + 8 * n, 0, 8 * tail, s) != hipSuccess ||
-         hipMemsetAsync(db + 8 * n, 0, 8 * tail, s) != hipSuccess ||
-         hipMemsetAsync(dc + 4 * n, 0, 4 * tail, s) != hipSuccess ||
-         hipMemsetAsync(dd + n, 0, tail, s) != hipSuccess))
-      rc = fps_fail(FPS_E_DEVICE, "hipMemsetAsync failed");
+    if (!rc) rc = fps_library_zero_tail(L, s);
     if (!rc && hipStreamSynchronize(s) != hipSuccess)
       rc = fps_fail(FPS_E_DEVICE, "stream synchronize failed");
     (void)hipHostFree(pin);
