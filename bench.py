@@ -142,7 +142,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=PAPER_N)
     ap.add_argument("--only", default="all",
-                    help="comma list of: small,single,shard,batch,uneven,serve,ingest,cpu")
+                    help="comma list of: small,single,shard,batch,uneven,serve,ingest,cluster,cpu")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--serve-warmup", type=float, default=1.0,
@@ -162,7 +162,7 @@ def main():
               "the engine runs on one GPU and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     legs = set(args.only.split(",")) if args.only != "all" else {
-        "small", "single", "shard", "batch", "uneven", "serve", "ingest", "cpu"}
+        "small", "single", "shard", "batch", "uneven", "serve", "ingest", "cluster", "cpu"}
 
     import torch
     import fpsynth
@@ -383,6 +383,10 @@ def main():
     if "serve" in legs:
         out["serving"] = serve(lib, lib_np, args, fps, fpsynth)
 
+    # ---------------- batch clustering search ----------------
+    if "cluster" in legs:
+        out["cluster"] = cluster_leg(lib, lib_np, fps, fpsynth)
+
     # ---------------- library file ingest ----------------
     if "ingest" in legs:
         out["ingest"] = ingest_leg(lib, lib_np, strides, fps, fpsynth)
@@ -409,6 +413,34 @@ def main():
         line["single"] = single
     print(json.dumps(line), flush=True)
     lib.close()
+
+
+def cluster_leg(lib, lib_np, fps, fpsynth):
+    """Batch clustering search (Section 4.4, Fig. 2): the 1024-query batch
+    clustered for every count 2..8 (k-medians, silhouette), then the top-30 of
+    every chosen center over the whole library."""
+    import torch
+    q = fpsynth.batch_queries(lib_np, 1024, 1003).words
+    fps.cluster(q, 2, 8)  # warm-up
+    torch.cuda.synchronize()
+    tc = []
+    for _ in range(5):
+        t = time.perf_counter()
+        res = fps.cluster(q, 2, 8)
+        tc.append(time.perf_counter() - t)
+    lib.cluster_search(q, 30, 2, 8)
+    ts = []
+    for _ in range(5):
+        t = time.perf_counter()
+        full = lib.cluster_search(q, 30, 2, 8)
+        ts.append(time.perf_counter() - t)
+    r = {"queries": 1024, "k": 30, "counts_tried": [2, 8], "chosen_k": res["K"],
+         "rounds": res["rounds"], "scores": {str(k): v for k, v in res["scores"].items()},
+         "cluster_ms": float(np.median(tc)) * 1000,
+         "cluster_search_ms": float(np.median(ts)) * 1000,
+         "same_clustering_in_search": bool(np.array_equal(full["labels"], res["labels"]))}
+    log("cluster:", json.dumps(r))
+    return r
 
 
 def ingest_leg(lib, lib_np, strides, fps, fpsynth):
@@ -602,6 +634,11 @@ def cpu_baseline(lib_np, qs, args, fpsynth):
     t1 = time.perf_counter()
     oracle.search(lib_np.words[:n1], qs[0], 30, nthreads=1)
     el1 = time.perf_counter() - t1
+    # batch clustering of the 1024-query batch (counts 2..8), the oracle's form
+    import oracle.cluster as ocl
+    tcl = time.perf_counter()
+    ocl.cluster(bq, 2, 8)
+    ecl = time.perf_counter() - tcl
     r = {"value": rs / es / 1e9, "unit": "G fp-compares/s", "cores": nth,
          "kind": "oracle",
          "sample": f"{ds} full-library single queries (top-30 over {n} records), "
@@ -616,6 +653,8 @@ def cpu_baseline(lib_np, qs, args, fpsynth):
                         "queries_s": du / eu},
          "one_core": {"value": n1 / el1 / 1e9, "sample": f"one query over {n1} records, "
                                                          f"serial form, {el1:.1f}s"},
+         "cluster1024": {"seconds": ecl, "sample": "clustering of the whole 1024-query batch "
+                                                   "for counts 2..8 (oracle/cluster.py)"},
          "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
     log("cpu:", json.dumps(r))
     return r

@@ -345,6 +345,75 @@ fps_status fps_tune(fps_library *lib, uint32_t q, const uint32_t *k, const uint3
                     void *workspace, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Batch clustering search (Section 4.4; Fig. 2).                             */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Section 4.4 describes a "batch clustering search": a batch of targets is
+ * clustered and the top 30 molecules are found per cluster; Fig. 2 picks the
+ * number of clusters ("categories") by the silhouette ("contour coefficient").
+ * The paper names neither the algorithm nor what is searched for a cluster.
+ * These calls take:
+ *   - for every cluster count K in [k_min, k_max]: farthest-first initial
+ *     centers (target 0, then the target farthest from its nearest center,
+ *     ties to the lowest index) and k-medians under the Manhattan distance of
+ *     Section 4.3 (targets join the nearest center, ties to the lowest center;
+ *     a center becomes the key-wise strict majority of its members, the
+ *     median that minimises their summed distance; an empty cluster keeps its
+ *     center), until no label changes or max_iter rounds;
+ *   - the mean silhouette (Rousseeuw 1987: s = (b - a) / max(a, b); 0 for a
+ *     singleton cluster or max(a, b) = 0), each s from exact integer distance
+ *     sums, added in index order in double precision; the K with the largest
+ *     mean wins, ties to the smaller K;
+ *   - the chosen clusters' centers are then searched as targets (Fig. 3).
+ */
+#define FPS_CLUSTER_MAX_K 16
+#define FPS_CLUSTER_MAX_Q 16384
+
+typedef struct {
+  uint32_t k;      /* the chosen number of clusters */
+  uint32_t rounds; /* k-medians rounds of the chosen clustering */
+  double score[FPS_CLUSTER_MAX_K + 1]; /* score[K] = mean silhouette of K clusters (0 if not tried) */
+} fps_cluster_info;
+
+/* Device workspace bytes of fps_cluster for q targets (3 <= q <= FPS_CLUSTER_MAX_Q). */
+fps_status fps_cluster_workspace_bytes(uint32_t q, size_t *bytes);
+
+/*
+ * Clusters q targets (host memory, q x 3 words) on the GPU.
+ *   k_min, k_max: cluster counts tried, 2 <= k_min <= k_max <= FPS_CLUSTER_MAX_K,
+ *                 k_max < q;
+ *   max_iter:     k-medians rounds at most (>= 1; 100 is ample);
+ *   workspace:    device memory, 256-byte aligned, >= fps_cluster_workspace_bytes;
+ *   labels:       host, q entries: the cluster of every target (0..k-1);
+ *   centers:      host, room for k_max x 3 words: the chosen centers;
+ *   info:         host (may be NULL): the chosen k, its rounds, every score.
+ * Synchronous on stream.  Errors: FPS_E_ARG, FPS_E_FINGERPRINT, FPS_E_NOMEM,
+ * FPS_E_DEVICE.
+ */
+fps_status fps_cluster(const uint64_t *queries, uint32_t q, uint32_t k_min, uint32_t k_max,
+                       uint32_t max_iter, void *workspace, size_t ws_bytes, void *stream,
+                       uint32_t *labels, uint64_t *centers, fps_cluster_info *info);
+
+/* Workspace bytes of fps_cluster_search: the larger of the clustering's and
+ * that of a search of k_max targets with result count k and stride mask. */
+fps_status fps_cluster_search_workspace_bytes(const fps_library *lib, uint32_t q, uint32_t k_max,
+                                              uint32_t k, uint32_t mask, size_t *bytes);
+
+/*
+ * fps_cluster, then the top-k of every chosen center over the strides of mask
+ * (the batch clustering search of Section 4.4).  out / out_capacity /
+ * out_offset as fps_search_batch for info->k targets (out_offset needs
+ * k_max + 1 entries); category c's hits are out[out_offset[c] ..
+ * out_offset[c+1]).  Errors: those of fps_cluster and fps_search_batch.
+ */
+fps_status fps_cluster_search(fps_library *lib, const uint64_t *queries, uint32_t q,
+                              uint32_t k_min, uint32_t k_max, uint32_t max_iter, uint32_t k,
+                              uint32_t mask, void *workspace, size_t ws_bytes, fps_hit *out,
+                              uint64_t out_capacity, uint64_t *out_offset, uint32_t *labels,
+                              uint64_t *centers, fps_cluster_info *info, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Tuning knobs, for tests that must force the rare paths.                   */
 /* ------------------------------------------------------------------------ */
 

@@ -71,6 +71,21 @@ class ServerStats(ctypes.Structure):
                 ("untuned_batches", ctypes.c_uint64)]
 
 
+CLUSTER_MAX_K = 16
+CLUSTER_MAX_Q = 16384
+
+
+class ClusterInfo(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_uint32), ("rounds", ctypes.c_uint32),
+                ("score", ctypes.c_double * (CLUSTER_MAX_K + 1))]
+
+
+def _cluster_result(info, labels, centers, k_min, k_max):
+    return {"K": int(info.k), "labels": labels.astype(np.int64), "rounds": int(info.rounds),
+            "centers": centers[:info.k].copy(),
+            "scores": {K: float(info.score[K]) for K in range(k_min, k_max + 1)}}
+
+
 EXPORTS = {
     # name: (restype, argtypes)
     "fps_library_device_bytes": (ctypes.c_size_t, [ctypes.c_uint64]),
@@ -128,6 +143,20 @@ EXPORTS = {
     "fps_parse_query": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t, ctypes.c_void_p]),
     "fps_parse_queries": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t, ctypes.c_void_p,
                                          ctypes.c_uint32, ctypes.c_void_p]),
+    "fps_cluster_workspace_bytes": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_void_p]),
+    "fps_cluster": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                   ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
+                                   ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p]),
+    "fps_cluster_search_workspace_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32,
+                                                          ctypes.c_uint32, ctypes.c_uint32,
+                                                          ctypes.c_uint32, ctypes.c_void_p]),
+    "fps_cluster_search": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                          ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                          ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
+                                          ctypes.c_size_t, ctypes.c_void_p, ctypes.c_uint64,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p]),
     "fps_last_error": (ctypes.c_char_p, []),
 }
 
@@ -410,6 +439,32 @@ class Library:
         out["distance"] = h["distance"]
         return out
 
+    def cluster_search(self, queries, k: int = 30, k_min: int = 2, k_max: int = 8,
+                       mask: int = MASK_ALL, max_iter: int = 100, stream=None) -> dict:
+        """Batch clustering search (Section 4.4): the clustering of cluster()
+        plus hits[c], the top-k of every chosen center c (fps_cluster_search)."""
+        c = load_library()
+        qs = np.ascontiguousarray(np.asarray(queries, dtype=np.uint64).reshape(-1, 3))
+        nq = qs.shape[0]
+        nb = ctypes.c_size_t()
+        _check(c.fps_cluster_search_workspace_bytes(self._handle, nq, int(k_max), int(k),
+                                                    int(mask), ctypes.byref(nb)))
+        ws = self._workspace(int(nb.value))
+        cap = max(1, int(k) * int(k_max))
+        out = np.empty(cap, dtype=HIT_DTYPE)
+        off = np.zeros(int(k_max) + 1, dtype=np.uint64)
+        labels = np.zeros(nq, dtype=np.uint32)
+        centers = np.zeros((max(k_max, 1), 3), dtype=np.uint64)
+        info = ClusterInfo()
+        _check(c.fps_cluster_search(self._handle, _ptr(qs), nq, int(k_min), int(k_max),
+                                    int(max_iter), int(k), int(mask),
+                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(), _ptr(out), cap,
+                                    _ptr(off), _ptr(labels), _ptr(centers), ctypes.byref(info),
+                                    _stream(stream, self._device)))
+        res = _cluster_result(info, labels, centers, k_min, k_max)
+        res["hits"] = [out[int(off[i]):int(off[i + 1])].copy() for i in range(res["K"])]
+        return res
+
     def search_batch(self, queries, k, mask=None, stream=None):
         """Independent top-k per query.  Returns (hits, offsets): query i's hits
         are hits[offsets[i]:offsets[i+1]]."""
@@ -432,6 +487,26 @@ class Library:
         # a view (no second copy of up to sum(k) hits); it is the whole array
         # unless some query has fewer than k records in its strides
         return out[:int(off[-1])], off
+
+
+def cluster(queries, k_min: int = 2, k_max: int = 8, max_iter: int = 100, stream=None) -> dict:
+    """Batch clustering (Section 4.4, Fig. 2) on the GPU: the chosen cluster
+    count K, every target's label, the K centers, the k-medians rounds and the
+    mean silhouette of every count tried (fps_cluster)."""
+    torch = _require_gpu()
+    c = load_library()
+    qs = np.ascontiguousarray(np.asarray(queries, dtype=np.uint64).reshape(-1, 3))
+    nq = qs.shape[0]
+    nb = ctypes.c_size_t()
+    _check(c.fps_cluster_workspace_bytes(nq, ctypes.byref(nb)))
+    ws = torch.empty(int(nb.value), dtype=torch.uint8, device="cuda")
+    labels = np.zeros(nq, dtype=np.uint32)
+    centers = np.zeros((max(k_max, 1), 3), dtype=np.uint64)
+    info = ClusterInfo()
+    _check(c.fps_cluster(_ptr(qs), nq, int(k_min), int(k_max), int(max_iter),
+                         ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream),
+                         _ptr(labels), _ptr(centers), ctypes.byref(info)))
+    return _cluster_result(info, labels, centers, k_min, k_max)
 
 
 def clock_ns() -> int:
