@@ -61,6 +61,12 @@ def _load():
         lib.fpsynth_text_write.argtypes = [vp, vp, u64, i32, ctypes.c_char_p, u64, i32, i32,
                                            vp, i32]
         lib.fpsynth_text_write.restype = i32
+        lib.fpsynth_wide_library.argtypes = [u64, u64, ctypes.c_uint32, vp, dbl, i32, i32, vp, vp,
+                                             vp, i32]
+        lib.fpsynth_wide_library.restype = i32
+        lib.fpsynth_wide_queries.argtypes = [u64, u64, vp, u64, ctypes.c_uint32, vp, vp, i32, i32,
+                                             vp, vp, vp]
+        lib.fpsynth_wide_queries.restype = i32
         _lib = lib
     return _lib
 
@@ -252,3 +258,65 @@ def query_text(words, width: int = 166, trailing_comma: bool = True, spaces: boo
     vals = [str((w[j >> 6] >> (j & 63)) & 1) for j in range(first, NKEYS + 1)]
     s = (", " if spaces else ",").join(vals)
     return "[" + s + ("," if trailing_comma else "") + "]"
+
+
+# --------------------------------------------------------------------------
+# Wider fingerprints (Section 5, concluding remark 3: more features), e.g.
+# 1,024 or 2,048 bits: W 64-bit words per record, every bit a key.  Per-bit
+# set probabilities p_j ~ Beta(0.3, 8.0) (about 3.6 % of the bits set, the
+# sparse shape of hashed circular fingerprints), quantised to multiples of
+# 1/256; 5 % near-duplicates with 0-3 distinct flips, as for MACCS.
+# --------------------------------------------------------------------------
+def wide_thresholds(words: int, seed: int) -> np.ndarray:
+    rng = np.random.default_rng([seed, 0x77696465])
+    p = rng.beta(0.3, 8.0, size=64 * words)
+    return np.clip(np.floor(p * 256.0), 0, 255).astype(np.uint8)
+
+
+@dataclass
+class WideLibrary:
+    words: np.ndarray          # (n, W) uint64
+    thr8: np.ndarray           # (64 W,) per-bit 8-bit thresholds
+    seed: int
+    dup_src: np.ndarray | None = None
+    dup_flips: np.ndarray | None = None
+
+    @property
+    def n(self) -> int:
+        return int(self.words.shape[0])
+
+    @property
+    def W(self) -> int:
+        return int(self.words.shape[1])
+
+
+def make_wide_library(n: int, words: int, seed: int, dup_frac: float = 0.05, flips=(0, 3),
+                      keep_meta: bool = True, nthreads: int | None = None) -> WideLibrary:
+    c = _load()
+    thr = wide_thresholds(words, seed)
+    out = np.empty((n, words), dtype=np.uint64)
+    src = np.empty(n, dtype=np.int32) if keep_meta else None
+    fl = np.empty(n, dtype=np.uint8) if keep_meta else None
+    rc = c.fpsynth_wide_library(seed, n, words, _ptr(thr), float(dup_frac), int(flips[0]),
+                                int(flips[1]), _ptr(out), _ptr(src), _ptr(fl),
+                                nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("fpsynth_wide_library rejected its arguments")
+    return WideLibrary(words=out, thr8=thr, seed=seed, dup_src=src, dup_flips=fl)
+
+
+def make_wide_queries(lib: WideLibrary, nq: int, seed: int, flips=(1, 8), fresh=None):
+    """Library records with flipped keys (or fresh draws where fresh[q] != 0):
+    returns (words (nq, W), src (nq,), flips (nq,))."""
+    c = _load()
+    W = lib.W
+    out = np.empty((nq, W), dtype=np.uint64)
+    src = np.empty(nq, dtype=np.int64)
+    fl = np.empty(nq, dtype=np.uint8)
+    fr = (np.arange(nq) % 2).astype(np.uint8) if fresh is None else np.asarray(fresh, np.uint8)
+    words = np.ascontiguousarray(lib.words)
+    rc = c.fpsynth_wide_queries(seed, nq, _ptr(words), lib.n, W, _ptr(lib.thr8), _ptr(fr),
+                                int(flips[0]), int(flips[1]), _ptr(out), _ptr(src), _ptr(fl))
+    if rc != 0:
+        raise ValueError("fpsynth_wide_queries rejected its arguments")
+    return out, src, fl

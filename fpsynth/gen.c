@@ -275,3 +275,122 @@ int fpsynth_text_write(const uint64_t *words, const uint64_t *ids, uint64_t n, i
   for (int t = 1; t < nthreads; ++t) pthread_join(th[t], NULL);
   return 0;
 }
+
+/*
+ * Wider fingerprints (records of `words` 64-bit words, every bit a key): key j
+ * is set iff an 8-bit uniform draw is below thr8[j] (probability thr8[j] / 256;
+ * eight draws per SplitMix64 output).  Near-duplicates as above: with
+ * probability dup_frac a record (index > 0) copies a uniformly chosen earlier
+ * record and flips F distinct keys, F uniform in [flip_lo, flip_hi].
+ */
+#define TAG_WIDE 0x77696465ULL  /* "wide" */
+
+static void wide_fresh(uint64_t key, const uint8_t *thr8, uint32_t words, uint64_t *out) {
+  for (uint32_t w = 0; w < words; ++w) {
+    uint64_t v = 0;
+    for (uint32_t g = 0; g < 8; ++g) {
+      uint64_t r = splitmix64(key + 8 * (uint64_t)w + g);
+      for (uint32_t b = 0; b < 8; ++b) {
+        uint32_t j = 64 * w + 8 * g + b;
+        if ((uint32_t)((r >> (8 * b)) & 0xFFu) < thr8[j]) v |= 1ULL << (8 * g + b);
+      }
+    }
+    out[w] = v;
+  }
+}
+
+static void wide_flip(uint64_t key, int nflips, uint32_t words, uint64_t *rec) {
+  uint32_t pos[64];
+  int got = 0;
+  uint64_t ctr = 0;
+  while (got < nflips) {
+    uint32_t j = (uint32_t)below(splitmix64(key + 1000 + ctr++), 64ULL * words);
+    int dup = 0;
+    for (int a = 0; a < got; ++a) dup |= (pos[a] == j);
+    if (dup) continue;
+    pos[got++] = j;
+    rec[j >> 6] ^= 1ULL << (j & 63);
+  }
+}
+
+typedef struct {
+  uint64_t seed, begin, end;
+  const uint8_t *thr8;
+  uint32_t words;
+  uint64_t *out;
+} wide_job;
+
+static void *wide_worker(void *arg) {
+  wide_job *jb = (wide_job *)arg;
+  for (uint64_t i = jb->begin; i < jb->end; ++i)
+    wide_fresh(stream_key(jb->seed, TAG_WIDE, i), jb->thr8, jb->words,
+               jb->out + (uint64_t)jb->words * i);
+  return NULL;
+}
+
+int fpsynth_wide_library(uint64_t seed, uint64_t n, uint32_t words, const uint8_t *thr8,
+                         double dup_frac, int flip_lo, int flip_hi, uint64_t *out,
+                         int32_t *dup_src, uint8_t *dup_flips, int nthreads) {
+  if (!thr8 || !out || words < 1 || words > 32 || flip_lo < 0 || flip_hi < flip_lo ||
+      flip_hi > 64)
+    return -1;
+  if (nthreads < 1) nthreads = 1;
+  if (nthreads > 256) nthreads = 256;
+  pthread_t th[256];
+  wide_job jobs[256];
+  for (int t = 0; t < nthreads; ++t) {
+    jobs[t].seed = seed;
+    jobs[t].begin = n * (uint64_t)t / (uint64_t)nthreads;
+    jobs[t].end = n * (uint64_t)(t + 1) / (uint64_t)nthreads;
+    jobs[t].thr8 = thr8;
+    jobs[t].words = words;
+    jobs[t].out = out;
+  }
+  for (int t = 1; t < nthreads; ++t) pthread_create(&th[t], NULL, wide_worker, &jobs[t]);
+  wide_worker(&jobs[0]);
+  for (int t = 1; t < nthreads; ++t) pthread_join(th[t], NULL);
+  const uint64_t cut = (uint64_t)(dup_frac * 9007199254740992.0);
+  for (uint64_t i = 0; i < n; ++i) {
+    int32_t src = -1;
+    int nf = 0;
+    if (i > 0) {
+      uint64_t key = stream_key(seed, TAG_DUP ^ TAG_WIDE, i);
+      if ((splitmix64(key) >> 11) < cut) {
+        src = (int32_t)below(splitmix64(key + 1), i);
+        nf = flip_lo + (int)below(splitmix64(key + 2), (uint64_t)(flip_hi - flip_lo + 1));
+        memcpy(out + (uint64_t)words * i, out + (uint64_t)words * (uint64_t)src,
+               words * sizeof(uint64_t));
+        wide_flip(key, nf, words, out + (uint64_t)words * i);
+      }
+    }
+    if (dup_src) dup_src[i] = src;
+    if (dup_flips) dup_flips[i] = (uint8_t)nf;
+  }
+  return 0;
+}
+
+int fpsynth_wide_queries(uint64_t seed, uint64_t nq, const uint64_t *lib, uint64_t n,
+                         uint32_t words, const uint8_t *thr8, const uint8_t *fresh, int flip_lo,
+                         int flip_hi, uint64_t *out, int64_t *src, uint8_t *flips) {
+  if (!thr8 || !out || !fresh || words < 1 || words > 32 || flip_lo < 0 || flip_hi < flip_lo ||
+      flip_hi > 64)
+    return -1;
+  for (uint64_t q = 0; q < nq; ++q) {
+    uint64_t key = stream_key(seed, TAG_QRY ^ TAG_WIDE, q);
+    uint64_t *rec = out + (uint64_t)words * q;
+    if (fresh[q]) {
+      wide_fresh(splitmix64(key + 7), thr8, words, rec);
+      if (src) src[q] = -1;
+      if (flips) flips[q] = 0;
+      continue;
+    }
+    if (!lib || n == 0) return -1;
+    uint64_t s = below(splitmix64(key), n);
+    int nf = flip_lo + (int)below(splitmix64(key + 1), (uint64_t)(flip_hi - flip_lo + 1));
+    memcpy(rec, lib + (uint64_t)words * s, words * sizeof(uint64_t));
+    wide_flip(key, nf, words, rec);
+    if (src) src[q] = (int64_t)s;
+    if (flips) flips[q] = (uint8_t)nf;
+  }
+  return 0;
+}

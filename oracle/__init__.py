@@ -80,6 +80,12 @@ class Oracle:
         lib.oracle_search_batch.restype = i32
         lib.oracle_read_text.argtypes = [vp, u64, vp, vp, u64, vp, vp]
         lib.oracle_read_text.restype = ctypes.c_int64
+        lib.oracle_distance_w.argtypes = [vp, vp, u32]
+        lib.oracle_distance_w.restype = u32
+        lib.oracle_distances_w.argtypes = [vp, u32, u64, u64, vp, vp]
+        lib.oracle_distances_w.restype = None
+        lib.oracle_search_w.argtypes = [vp, u32, vp, vp, u32, vp, u64, vp, i32]
+        lib.oracle_search_w.restype = ctypes.c_int64
         self._lib = lib
 
     def distance(self, a, b) -> int:
@@ -143,6 +149,57 @@ class Oracle:
         if rc != 0:
             raise MemoryError("oracle_search_batch ran out of memory")
         return out[:int(off[-1])].copy(), off
+
+    # -- wider fingerprints (Section 5, remark 3): records of W words, keys 0..64W-1 --
+    def distance_w(self, a, b) -> int:
+        a = np.ascontiguousarray(np.asarray(a, dtype=np.uint64).reshape(-1))
+        b = np.ascontiguousarray(np.asarray(b, dtype=np.uint64).reshape(-1))
+        assert a.shape == b.shape
+        return int(self._lib.oracle_distance_w(_p(a), _p(b), a.shape[0]))
+
+    def distances_w(self, lib_words: np.ndarray, query, begin: int = 0,
+                    end: int | None = None) -> np.ndarray:
+        w = np.ascontiguousarray(lib_words, dtype=np.uint64)
+        W = w.shape[1]
+        end = w.shape[0] if end is None else end
+        q = np.ascontiguousarray(np.asarray(query, dtype=np.uint64).reshape(W))
+        out = np.empty(end - begin, dtype=np.uint32)
+        self._lib.oracle_distances_w(_p(w), W, begin, end, _p(q), _p(out))
+        return out
+
+    def search_w(self, lib_words: np.ndarray, query, k: int, ranges=None,
+                 nthreads: int = 1) -> np.ndarray:
+        """Top-k of one W-word query over (n, W) records, as search()."""
+        w = np.ascontiguousarray(lib_words, dtype=np.uint64)
+        W = w.shape[1]
+        if ranges is None:
+            ranges = [(0, w.shape[0])]
+        b = np.array([r[0] for r in ranges], dtype=np.uint64)
+        e = np.array([r[1] for r in ranges], dtype=np.uint64)
+        total = int((e - b).sum()) if len(ranges) else 0
+        out = np.empty(max(min(int(k), total), 1), dtype=HIT_DTYPE)
+        q = np.ascontiguousarray(np.asarray(query, dtype=np.uint64).reshape(W))
+        got = self._lib.oracle_search_w(_p(w), W, _p(b), _p(e), len(ranges), _p(q), int(k),
+                                        _p(out), int(nthreads))
+        if got < 0:
+            raise MemoryError("oracle_search_w ran out of memory")
+        return out[:got].copy()
+
+    def search_batch_w(self, lib_words, queries, k, strides=None, masks=None, nthreads: int = 1):
+        """Independent top-k per W-word query: (hits, offsets) as search_batch()."""
+        w = np.ascontiguousarray(lib_words, dtype=np.uint64)
+        qs = np.ascontiguousarray(queries, dtype=np.uint64).reshape(-1, w.shape[1])
+        nq = qs.shape[0]
+        k = np.broadcast_to(np.asarray(k, dtype=np.int64), (nq,))
+        strides = [0, w.shape[0]] if strides is None else list(strides)
+        parts, off = [], [0]
+        for q in range(nq):
+            rr = mask_ranges(strides, None if masks is None else masks[q])
+            h = self.search_w(w, qs[q], int(k[q]), rr, nthreads)
+            parts.append(h)
+            off.append(off[-1] + len(h))
+        hits = np.concatenate(parts) if parts else np.empty(0, dtype=HIT_DTYPE)
+        return hits, np.array(off, dtype=np.uint64)
 
     def read_text(self, text):
         """Records of a library file (Fig. 3 step 1): (words (n, 3) uint64,
@@ -276,3 +333,19 @@ def search_batch(lib_words, queries, k, strides=None, masks=None, nthreads: int 
 
 def read_text(text):
     return default().read_text(text)
+
+
+def distance_w(a, b) -> int:
+    return default().distance_w(a, b)
+
+
+def distances_w(lib_words, query, begin: int = 0, end: int | None = None) -> np.ndarray:
+    return default().distances_w(lib_words, query, begin, end)
+
+
+def search_w(lib_words, query, k: int, ranges=None, nthreads: int = 1) -> np.ndarray:
+    return default().search_w(lib_words, query, k, ranges, nthreads)
+
+
+def search_batch_w(lib_words, queries, k, strides=None, masks=None, nthreads: int = 1):
+    return default().search_batch_w(lib_words, queries, k, strides, masks, nthreads)

@@ -270,3 +270,103 @@ int64_t oracle_read_text(const char *text, uint64_t len, uint64_t *words, uint64
   }
   return (int64_t)n;
 }
+
+/*
+ * Wider fingerprints (Section 5, concluding remark 3: more features): records
+ * of `words` 64-bit words, keys 0 .. 64 * words - 1, key j at bit (j & 63) of
+ * word (j >> 6); every bit is a key.  The distance is again the Section 4.3
+ * sum, now over all 64 * words keys, and the top-k, tie rule, strides and the
+ * threaded combine-and-sort are those above.
+ */
+static int key_value_w(const uint64_t *rec, uint32_t j) {
+  return (int)((rec[j >> 6] >> (j & 63)) & 1u);
+}
+
+uint32_t oracle_distance_w(const uint64_t *a, const uint64_t *b, uint32_t words) {
+  int sum = 0;
+  for (uint32_t j = 0; j < 64 * words; ++j) {
+    int c = key_value_w(a, j) - key_value_w(b, j); /* Fig. 3 step 3 */
+    sum += (c < 0) ? -c : c;                       /* Fig. 3 step 4 */
+  }
+  return (uint32_t)sum;
+}
+
+void oracle_distances_w(const uint64_t *lib, uint32_t words, uint64_t begin, uint64_t end,
+                        const uint64_t *query, uint32_t *out) {
+  for (uint64_t i = begin; i < end; ++i)
+    out[i - begin] = oracle_distance_w(lib + (uint64_t)words * i, query, words);
+}
+
+static void search_ranges_w(const uint64_t *lib, uint32_t words, const uint64_t *begin,
+                            const uint64_t *end, uint32_t nranges, const uint64_t *query,
+                            topk_list *t) {
+  for (uint32_t r = 0; r < nranges; ++r)
+    for (uint64_t i = begin[r]; i < end[r]; ++i)
+      topk_offer(t, (uint32_t)i, oracle_distance_w(lib + (uint64_t)words * i, query, words));
+}
+
+typedef struct {
+  const uint64_t *lib;
+  const uint64_t *query;
+  uint32_t words;
+  uint64_t begin, end;
+  topk_list list;
+} chunk_job_w;
+
+static void *chunk_worker_w(void *arg) {
+  chunk_job_w *c = (chunk_job_w *)arg;
+  search_ranges_w(c->lib, c->words, &c->begin, &c->end, 1, c->query, &c->list);
+  return NULL;
+}
+
+/* oracle_search for records of `words` words (arguments as oracle_search). */
+int64_t oracle_search_w(const uint64_t *lib, uint32_t words, const uint64_t *begin,
+                        const uint64_t *end, uint32_t nranges, const uint64_t *query, uint64_t k,
+                        oracle_hit *out, int nthreads) {
+  uint64_t total = 0;
+  for (uint32_t r = 0; r < nranges; ++r) total += end[r] - begin[r];
+  uint64_t want = k < total ? k : total;
+  topk_list t = {out, 0, want};
+  if (nthreads <= 1 || total < 4096) {
+    search_ranges_w(lib, words, begin, end, nranges, query, &t);
+    return (int64_t)t.len;
+  }
+  if (nthreads > 256) nthreads = 256;
+  chunk_job_w *jobs = (chunk_job_w *)calloc((size_t)nthreads * nranges, sizeof(chunk_job_w));
+  pthread_t *th = (pthread_t *)calloc((size_t)nthreads * nranges, sizeof(pthread_t));
+  if (!jobs || !th) {
+    free(jobs);
+    free(th);
+    return -1;
+  }
+  int njobs = 0, failed = 0;
+  for (uint32_t r = 0; r < nranges; ++r) {
+    uint64_t len = end[r] - begin[r];
+    int parts = (int)((len * (uint64_t)nthreads + total - 1) / total);
+    if (parts < 1) parts = 1;
+    for (int p = 0; p < parts; ++p) {
+      chunk_job_w *c = &jobs[njobs++];
+      c->lib = lib;
+      c->query = query;
+      c->words = words;
+      c->begin = begin[r] + len * (uint64_t)p / (uint64_t)parts;
+      c->end = begin[r] + len * (uint64_t)(p + 1) / (uint64_t)parts;
+      c->list.cap = want;
+      c->list.len = 0;
+      c->list.h = (oracle_hit *)malloc((want ? want : 1) * sizeof(oracle_hit));
+      if (!c->list.h) failed = 1;
+    }
+  }
+  if (!failed) {
+    for (int j = 1; j < njobs; ++j) pthread_create(&th[j], NULL, chunk_worker_w, &jobs[j]);
+    chunk_worker_w(&jobs[0]);
+    for (int j = 1; j < njobs; ++j) pthread_join(th[j], NULL);
+    for (int j = 0; j < njobs; ++j) /* combine and sort (Section 4.3) */
+      for (uint64_t i = 0; i < jobs[j].list.len; ++i)
+        topk_offer(&t, jobs[j].list.h[i].index, jobs[j].list.h[i].distance);
+  }
+  for (int j = 0; j < njobs; ++j) free(jobs[j].list.h);
+  free(jobs);
+  free(th);
+  return failed ? -1 : (int64_t)t.len;
+}

@@ -380,10 +380,80 @@ def pin_query_list(orc):
     assert many.shape == (2, 3) and key_set(many[1]) == {166}
 
 
+# ---------------- wider fingerprints (Section 5, remark 3) ----------------
+WIDTHS = (2, 16, 32)
+
+
+def wide_int(rec) -> int:
+    return sum(int(x) << (64 * w) for w, x in enumerate(np.asarray(rec, dtype=np.uint64)))
+
+
+def wide_pack(keys, W) -> np.ndarray:
+    v = 0
+    for j in keys:
+        v |= 1 << j
+    return np.array([(v >> (64 * w)) & ((1 << 64) - 1) for w in range(W)], dtype=np.uint64)
+
+
+def pin_wide_set_algebra(orc):
+    rnd = random.Random(31)
+    for W in WIDTHS:
+        n = 64 * W
+        for _ in range(150):
+            a = set(rnd.sample(range(n), rnd.randint(0, n)))
+            b = set(rnd.sample(range(n), rnd.randint(0, n)))
+            assert orc.distance_w(wide_pack(a, W), wide_pack(b, W)) == len(a ^ b), W
+        full = wide_pack(range(n), W)
+        empty = wide_pack([], W)
+        assert orc.distance_w(full, empty) == n
+        for j in (0, 1, 63, 64, n - 1):
+            assert orc.distance_w(wide_pack([j], W), empty) == 1, (W, j)
+
+
+def pin_wide_broadcast_topk(orc):
+    for W in WIDTHS:
+        lib = fpsynth.make_wide_library(6000, W, W)
+        qs, _, _ = fpsynth.make_wide_queries(lib, 3, 5)
+        A = np.unpackbits(lib.words.view(np.uint8), axis=1, bitorder="little").astype(np.int16)
+        for q in qs:
+            b = np.unpackbits(q.view(np.uint8), bitorder="little").astype(np.int16)
+            K = np.abs(A - b).sum(axis=1)  # Section 4.3: C = A - b, K = SUM(ABS(C))
+            assert np.array_equal(orc.distances_w(lib.words, q).astype(np.int64), K), W
+            for k in (1, 30, 1000, 6000, 6005):
+                idx, dist = lexsort_topk(K, k)
+                assert_hits(orc.search_w(lib.words, q, k), idx, dist, f"W {W} k {k}")
+                if k in (30, 1000):
+                    assert np.array_equal(orc.search_w(lib.words, q, k, nthreads=8),
+                                          orc.search_w(lib.words, q, k))
+
+
+def pin_wide_strides_and_planted(orc):
+    W = 16
+    lib = fpsynth.make_wide_library(20_000, W, 7)
+    strides = [0, 7000, 12000, 20_000]
+    qs, src, fl = fpsynth.make_wide_queries(lib, 4, 9, flips=(0, 6), fresh=np.zeros(4))
+    for qi in range(4):
+        assert orc.distance_w(qs[qi], lib.words[src[qi]]) == fl[qi]
+        for mask in (1, 3, 5, 7):
+            rr = [(strides[s], strides[s + 1]) for s in range(3) if (mask >> s) & 1]
+            parts = []
+            for lo, hi in rr:
+                d = orc.distances_w(lib.words, qs[qi], lo, hi).astype(np.int64)
+                idx, dist = lexsort_topk(d, 30, index_base=lo)
+                parts += list(zip(dist.tolist(), idx.tolist()))
+            parts.sort()
+            h = orc.search_w(lib.words, qs[qi], 30, ranges=rr, nthreads=4)
+            assert_hits(h, [p[1] for p in parts[:30]], [p[0] for p in parts[:30]], f"mask {mask}")
+    dups = np.nonzero(lib.dup_src >= 0)[0][:500]
+    for i in dups:
+        assert orc.distance_w(lib.words[i], lib.words[lib.dup_src[i]]) == lib.dup_flips[i]
+
+
 ALL_PINS = [
     pin_set_algebra, pin_special_cases, pin_bitcount_identities, pin_metric_axioms,
     pin_paper_broadcast_distances, pin_paper_broadcast_topk, pin_histogram_invariant,
     pin_planted_distances, pin_fig2_column, pin_chunked_equals_serial, pin_strides_merge,
     pin_k_edges, pin_identical_rows, pin_batch_equals_single,
     pin_text_handwritten, pin_text_errors, pin_text_roundtrip, pin_query_list,
+    pin_wide_set_algebra, pin_wide_broadcast_topk, pin_wide_strides_and_planted,
 ]

@@ -31,6 +31,12 @@ MUTATIONS = {
     "text_tail_unchecked": ("if (!is_blank(s[t])) return 6;", "if (s[t] == 0) return 6;"),
     "text_no_cr": ("c == ' ' || c == '\\t' || c == '\\r'; }", "c == ' ' || c == '\\t'; }"),
     "text_key0_unchecked": ("if (j == 0) return 5;", "if (j == 0) j = 0;"),
+    # wider fingerprints (Section 5, remark 3)
+    "wide_drop_last_key": ("j < 64 * words; ++j", "j < 64 * words - 1; ++j"),
+    "wide_wrong_word": ("rec[j >> 6] >> (j & 63)) & 1u);\n}\n\nuint32_t oracle_distance_w",
+                        "rec[j >> 7] >> (j & 63)) & 1u);\n}\n\nuint32_t oracle_distance_w"),
+    "wide_record_stride": ("topk_offer(t, (uint32_t)i, oracle_distance_w(lib + (uint64_t)words * i",
+                           "topk_offer(t, (uint32_t)i, oracle_distance_w(lib + (uint64_t)3 * i"),
 }
 
 RUNNER = r"""
