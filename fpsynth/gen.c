@@ -285,15 +285,25 @@ int fpsynth_text_write(const uint64_t *words, const uint64_t *ids, uint64_t n, i
  */
 #define TAG_WIDE 0x77696465ULL  /* "wide" */
 
+/* Bit b (0..7) of the result: byte b of r below byte b of t.  Even and odd
+ * bytes are compared in 16-bit lanes (the borrow of (r_b | 0x100) - t_b
+ * clears bit 8 iff r_b < t_b), then the eight flags are gathered. */
+static inline uint32_t bytes_below(uint64_t r, uint64_t t) {
+  const uint64_t M = 0x00FF00FF00FF00FFULL, H = 0x0100010001000100ULL;
+  const uint64_t lt_e = ~(((r & M) | H) - (t & M)) & H;
+  const uint64_t lt_o = ~((((r >> 8) & M) | H) - ((t >> 8) & M)) & H;
+  const uint64_t x = (lt_e >> 8) | (lt_o >> 7);
+  return (uint32_t)((x | (x >> 14) | (x >> 28) | (x >> 42)) & 0xFFu);
+}
+
 static void wide_fresh(uint64_t key, const uint8_t *thr8, uint32_t words, uint64_t *out) {
   for (uint32_t w = 0; w < words; ++w) {
     uint64_t v = 0;
     for (uint32_t g = 0; g < 8; ++g) {
       uint64_t r = splitmix64(key + 8 * (uint64_t)w + g);
-      for (uint32_t b = 0; b < 8; ++b) {
-        uint32_t j = 64 * w + 8 * g + b;
-        if ((uint32_t)((r >> (8 * b)) & 0xFFu) < thr8[j]) v |= 1ULL << (8 * g + b);
-      }
+      uint64_t t;
+      memcpy(&t, thr8 + 64 * w + 8 * g, 8);
+      v |= (uint64_t)bytes_below(r, t) << (8 * g);
     }
     out[w] = v;
   }

@@ -414,6 +414,72 @@ fps_status fps_cluster_search(fps_library *lib, const uint64_t *queries, uint32_
                               uint64_t *centers, fps_cluster_info *info, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Wider fingerprints (Section 5, concluding remark 3: more features).         */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Libraries of fingerprints of W 64-bit words, W in {4, 8, 16, 32} (256 to
+ * 2,048 keys, e.g. hashed circular fingerprints of 1,024 or 2,048 bits).
+ * Key j (0 .. 64 W - 1) is bit (j & 63) of word (j >> 6); every bit is a key,
+ * none is reserved.  The distance is the Section 4.3 sum over all 64 W keys
+ * (the number of differing keys, 0 .. 64 W), the top-k order, tie rule,
+ * strides and merge are those of the MACCS calls above, and the results are
+ * fps_hit (index, distance).  Device memory is caller-owned as above.
+ */
+#define FPS_WIDE_MAX_WORDS 32
+
+typedef struct fps_wide fps_wide; /* opaque handle */
+
+/* Device bytes of n records of `words` words: 8 * words bytes per record,
+ * word-major, n rounded up to a multiple of 4096. */
+size_t fps_wide_device_bytes(uint64_t n, uint32_t words);
+
+/* Uploads n records (host, n x words uint64, record-major) into device_buf in
+ * the engine's layout.  Arguments and errors as fps_library_load, plus
+ * FPS_E_ARG when words is not 4, 8, 16 or 32. */
+fps_status fps_wide_load(const uint64_t *host_words, uint64_t n, uint32_t words,
+                         const uint64_t *stride_begin, uint32_t nstrides, void *device_buf,
+                         size_t device_bytes, void *stream, fps_wide **out);
+
+/* Releases the handle (never device_buf).  NULL is OK. */
+fps_status fps_wide_free(fps_wide *lib);
+
+/* Scan kernel of a search: FPS_PATH_SINGLE (one query per pass), _POPCOUNT,
+ * _MFMA_I8, _MFMA_F4, or FPS_PATH_AUTO (default: single for 1-2 queries,
+ * popcount below 32, fp4 matrix cores from 32).  Results never depend on it. */
+fps_status fps_wide_set_path(fps_wide *lib, fps_path path);
+
+/* candidate_scale multiplies the candidate capacity (tiny values force the
+ * overflow fallback); sample_records is the bound sample (0 = 65,536);
+ * force_fallback != 0 answers every query with the exact two-pass fallback.
+ * Results never depend on these; workspace sizes do. */
+fps_status fps_wide_set_tuning(fps_wide *lib, double candidate_scale, uint64_t sample_records,
+                               int force_fallback);
+
+/* HIP-event timing of scan_ms / total_ms in the statistics (off by default). */
+fps_status fps_wide_set_timing(fps_wide *lib, int enable);
+
+/* Workspace bytes of a search of q queries with k[] and masks (NULL = all);
+ * depends on the path set with fps_wide_set_path. */
+fps_status fps_wide_workspace_bytes(const fps_wide *lib, uint32_t q, const uint32_t *k,
+                                    const uint32_t *mask, size_t *bytes);
+
+/* Independent queries (host, q x words uint64).  Arguments, results and errors
+ * as fps_search_batch. */
+fps_status fps_wide_search_batch(fps_wide *lib, const uint64_t *queries, uint32_t q,
+                                 const uint32_t *k, const uint32_t *mask, void *workspace,
+                                 size_t ws_bytes, fps_hit *out, uint64_t out_capacity,
+                                 uint64_t *out_offset, void *stream);
+
+/* One query (host, `words` uint64), as fps_search. */
+fps_status fps_wide_search(fps_wide *lib, const uint64_t *query, uint32_t k, uint32_t mask,
+                           void *workspace, size_t ws_bytes, fps_hit *out, uint32_t *n_out,
+                           void *stream);
+
+/* Counters of the last search on this handle, as fps_last_search_stats. */
+fps_status fps_wide_last_search_stats(const fps_wide *lib, fps_search_stats *stats);
+
+/* ------------------------------------------------------------------------ */
 /* Tuning knobs, for tests that must force the rare paths.                   */
 /* ------------------------------------------------------------------------ */
 

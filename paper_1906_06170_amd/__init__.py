@@ -143,6 +143,26 @@ EXPORTS = {
     "fps_parse_query": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t, ctypes.c_void_p]),
     "fps_parse_queries": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t, ctypes.c_void_p,
                                          ctypes.c_uint32, ctypes.c_void_p]),
+    "fps_wide_device_bytes": (ctypes.c_size_t, [ctypes.c_uint64, ctypes.c_uint32]),
+    "fps_wide_load": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
+                                     ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
+                                     ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]),
+    "fps_wide_free": (ctypes.c_int, [ctypes.c_void_p]),
+    "fps_wide_set_path": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "fps_wide_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_uint64,
+                                           ctypes.c_int]),
+    "fps_wide_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "fps_wide_workspace_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32,
+                                                ctypes.c_void_p, ctypes.c_void_p,
+                                                ctypes.c_void_p]),
+    "fps_wide_search_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_size_t, ctypes.c_void_p, ctypes.c_uint64,
+                                             ctypes.c_void_p, ctypes.c_void_p]),
+    "fps_wide_search": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                       ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fps_wide_last_search_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "fps_cluster_workspace_bytes": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_void_p]),
     "fps_cluster": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
                                    ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
@@ -507,6 +527,94 @@ def cluster(queries, k_min: int = 2, k_max: int = 8, max_iter: int = 100, stream
                          ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream),
                          _ptr(labels), _ptr(centers), ctypes.byref(info)))
     return _cluster_result(info, labels, centers, k_min, k_max)
+
+
+class WideLibrary:
+    """A library of wider fingerprints (W = 4, 8, 16 or 32 words: 256 to 2,048
+    keys, every bit a key) resident in HBM (Section 5, concluding remark 3)."""
+
+    def __init__(self, words: np.ndarray, strides=None, stream=None):
+        torch = _require_gpu()
+        c = load_library()
+        w = np.ascontiguousarray(words, dtype=np.uint64)
+        if w.ndim != 2:
+            raise ValueError("words must be (n, W)")
+        self.n, self.W = int(w.shape[0]), int(w.shape[1])
+        nbytes = int(c.fps_wide_device_bytes(self.n, self.W))
+        self._buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device="cuda")
+        self._device = self._buf.device.index
+        self._ws = None
+        self._handle = ctypes.c_void_p()
+        self.strides = [0, self.n] if strides is None else [int(x) for x in strides]
+        st = None if strides is None else np.ascontiguousarray(strides, dtype=np.uint64)
+        _check(c.fps_wide_load(_ptr(w), self.n, self.W, None if st is None else _ptr(st),
+                               0 if st is None else len(st) - 1,
+                               ctypes.c_void_p(self._buf.data_ptr()), nbytes, _stream(stream),
+                               ctypes.byref(self._handle)))
+
+    def close(self):
+        if self._handle:
+            load_library().fps_wide_free(self._handle)
+            self._handle = ctypes.c_void_p()
+        self._buf = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_path(self, path: int):
+        _check(load_library().fps_wide_set_path(self._handle, int(path)))
+
+    def set_tuning(self, candidate_scale: float = 1.0, sample_records: int = 0,
+                   force_fallback: bool = False):
+        _check(load_library().fps_wide_set_tuning(self._handle, float(candidate_scale),
+                                                  int(sample_records), int(bool(force_fallback))))
+
+    def set_timing(self, enable: bool):
+        _check(load_library().fps_wide_set_timing(self._handle, int(bool(enable))))
+
+    def last_stats(self) -> dict:
+        st = SearchStats()
+        _check(load_library().fps_wide_last_search_stats(self._handle, ctypes.byref(st)))
+        return {"path": PATH_NAMES.get(st.path, st.path), "queries": st.queries,
+                "fallbacks": st.fallbacks, "candidates": st.candidates, "scan_ms": st.scan_ms,
+                "total_ms": st.total_ms, "scan_launches": st.scan_launches,
+                "scan_ms_sum": st.scan_ms_sum, "total_ms_sum": st.total_ms_sum,
+                "calls": st.calls}
+
+    def _workspace(self, nbytes: int):
+        import torch
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = None
+            self._ws = torch.empty(max(nbytes, 1 << 20), dtype=torch.uint8, device="cuda")
+        return self._ws
+
+    def search_batch(self, queries, k, mask=None, stream=None):
+        """Independent top-k per query: (hits, offsets), as Library.search_batch."""
+        c = load_library()
+        qs = np.ascontiguousarray(np.asarray(queries, dtype=np.uint64).reshape(-1, self.W))
+        nq = qs.shape[0]
+        kk = _u32(k, nq)
+        mm = None if mask is None else _u32(mask, nq)
+        nb = ctypes.c_size_t()
+        _check(c.fps_wide_workspace_bytes(self._handle, nq, _ptr(kk),
+                                          None if mm is None else _ptr(mm), ctypes.byref(nb)))
+        ws = self._workspace(int(nb.value))
+        cap = int(kk.astype(np.uint64).sum())
+        out = np.empty(max(cap, 1), dtype=HIT_DTYPE)
+        off = np.zeros(nq + 1, dtype=np.uint64)
+        _check(c.fps_wide_search_batch(self._handle, _ptr(qs), nq, _ptr(kk),
+                                       None if mm is None else _ptr(mm),
+                                       ctypes.c_void_p(ws.data_ptr()), ws.numel(), _ptr(out), cap,
+                                       _ptr(off), _stream(stream, self._device)))
+        return out[:int(off[-1])], off
+
+    def search(self, query, k: int, mask: int = MASK_ALL, stream=None) -> np.ndarray:
+        h, _ = self.search_batch(np.asarray(query).reshape(1, self.W), [k], [mask], stream)
+        return h.copy()
 
 
 def clock_ns() -> int:

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "libfps.so")
-SOURCES = ["kernels.hip", "mfma.hip", "mfma_f4.hip", "runtime.hip", "server.hip", "text.hip", "cluster.hip"]
+SOURCES = ["kernels.hip", "mfma.hip", "mfma_f4.hip", "runtime.hip", "server.hip", "text.hip", "cluster.hip", "wide.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [
