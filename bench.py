@@ -142,7 +142,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=PAPER_N)
     ap.add_argument("--only", default="all",
-                    help="comma list of: small,single,shard,batch,uneven,serve,ingest,cluster,cpu")
+                    help="comma list of: small,single,shard,batch,uneven,serve,ingest,cluster,wide,"
+                         "cpu")
+    ap.add_argument("--wide-n", type=int, default=24_000_000,
+                    help="records of the 2,048-key library of the wide leg")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--serve-warmup", type=float, default=1.0,
@@ -162,7 +165,7 @@ def main():
               "the engine runs on one GPU and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     legs = set(args.only.split(",")) if args.only != "all" else {
-        "small", "single", "shard", "batch", "uneven", "serve", "ingest", "cluster", "cpu"}
+        "small", "single", "shard", "batch", "uneven", "serve", "ingest", "cluster", "wide", "cpu"}
 
     import torch
     import fpsynth
@@ -383,6 +386,10 @@ def main():
     if "serve" in legs:
         out["serving"] = serve(lib, lib_np, args, fps, fpsynth)
 
+    # ---------------- wider fingerprints ----------------
+    if "wide" in legs:
+        out["wide"] = wide_leg(fps, fpsynth, args)
+
     # ---------------- batch clustering search ----------------
     if "cluster" in legs:
         out["cluster"] = cluster_leg(lib, lib_np, fps, fpsynth)
@@ -413,6 +420,64 @@ def main():
         line["single"] = single
     print(json.dumps(line), flush=True)
     lib.close()
+
+
+def wide_leg(fps, fpsynth, args):
+    """Wider fingerprints (Section 5, concluding remark 3): 2,048 keys (32 words,
+    256 bytes) per record, every bit a key.  One query, top-30, end to end
+    through fps_wide_search; the scan kernel's duration from HIP events gives
+    its HBM roofline (256 bytes per record compared).  Then 256 queries in one
+    call on the fp4 matrix cores (2 x 2,048 operations per pair)."""
+    import torch
+    W, n = 32, args.wide_n
+    t = time.perf_counter()
+    lib_np = fpsynth.make_wide_library(n, W, 1, keep_meta=False)
+    gen_s = time.perf_counter() - t
+    lib = fps.WideLibrary(lib_np.words)
+    qs, _, _ = fpsynth.make_wide_queries(lib_np, 23, 2001, flips=(0, 8), fresh=np.zeros(23))
+    for i in range(3):
+        lib.search(qs[i], 30)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for i in range(3, 23):
+        lib.search(qs[i], 30)
+    ms = (time.perf_counter() - t) * 1000 / 20
+    lib.set_timing(True)
+    s0 = lib.last_stats()
+    for i in range(3, 23):
+        lib.search(qs[i], 30)
+    s1 = lib.last_stats()
+    scan_ms = (s1["scan_ms_sum"] - s0["scan_ms_sum"]) / 20
+    rec_bytes = 8 * W
+    gbs = rec_bytes * n / (scan_ms * 1e-3) / 1e9
+    r = {"records": n, "keys": 64 * W, "bytes_per_record": rec_bytes, "k": 30,
+         "library_gb": rec_bytes * n / 1e9, "generate_s": gen_s,
+         "ms_per_query": ms, "gcmp_s": n / (ms * 1e-3) / 1e9, "scan_ms_per_query": scan_ms,
+         "scan_launches_per_query": s1["scan_launches"],
+         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": gbs / HBM_PEAK_GBS, "kernel": "k_wscan1<32>"}}
+    # a batch on the matrix cores
+    bq, _, _ = fpsynth.make_wide_queries(lib_np, 256, 2003)
+    lib.set_path(fps.PATH_MFMA_F4)
+    lib.search_batch(bq, 30)
+    tb = []
+    for _ in range(3):
+        t = time.perf_counter()
+        lib.search_batch(bq, 30)
+        tb.append(time.perf_counter() - t)
+    st = lib.last_stats()
+    bms = float(np.median(tb)) * 1000
+    tops = 2 * 64 * W * 256.0 * n / (st["scan_ms"] * 1e-3) / 1e12
+    r["batch256"] = {"queries": 256, "path": st["path"], "ms": bms, "qps": 256 / (bms * 1e-3),
+                     "scan_ms": st["scan_ms"], "speedup_vs_single_qps": ms * 256 / bms,
+                     "roofline": {"bound": "mfma", "achieved": tops, "peak": FP4_PEAK_TFLOPS,
+                                  "unit": "TFLOP/s", "frac": tops / FP4_PEAK_TFLOPS,
+                                  "dtype": "fp4"}}
+    lib.close()
+    del lib_np
+    torch.cuda.empty_cache()
+    log("wide:", json.dumps(r))
+    return r
 
 
 def cluster_leg(lib, lib_np, fps, fpsynth):
