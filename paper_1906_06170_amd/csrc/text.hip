@@ -48,6 +48,9 @@ constexpr uint32_t kTextChunk = 16384;  // bytes per wave of the count kernel, p
 constexpr uint32_t kOverhang = 256;     // bytes past its chunk a line starting in it may use
 constexpr uint32_t kLineMax = 255;      // characters of a line before its '\n'
 constexpr uint32_t kIdDigits = 19;      // every 19-digit id fits in 64 bits
+
+__constant__ uint64_t kPow10u[10] = {1ull, 10ull, 100ull, 1000ull, 10000ull, 100000ull,
+                                     1000000ull, 10000000ull, 100000000ull, 1000000000ull};
 constexpr uint32_t kPrefixTile = 4096;    // chunk counts per block of the prefix kernels
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -283,22 +286,28 @@ __global__ __launch_bounds__(kParseThreads) void k_text_parse(const uint8_t *tex
   if (E - s > kLineMax) {
     kind = 1;
   } else {
-    // id: the run of digits at the start of the line (at most 20 looked at)
-    uint32_t e = 0;
+    // id: the run of digits at the start of the line (at most 20 looked at),
+    // accumulated nine digits at a time in 32-bit parts a, b, c
+    uint32_t e = 0, pa = 0, pb = 0, pc = 0;
     bool run = true;
 #pragma unroll
     for (uint32_t k = 0; k < 20; k += 4) {
       const uint32_t x = lds_u32(buf, s + k);
 #pragma unroll
       for (uint32_t b = 0; b < 4; ++b) {
-        const uint32_t ch = (x >> (8 * b)) & 0xFFu;
-        run = run && s + k + b < E && ch - '0' < 10u;
+        const uint32_t d = ((x >> (8 * b)) & 0xFFu) - '0';
+        run = run && s + k + b < E && d < 10u;
         if (run) {
-          id = id * 10u + (ch - '0');
+          if (k + b < 9) pa = pa * 10u + d;
+          else if (k + b < 18) pb = pb * 10u + d;
+          else pc = pc * 10u + d;
           ++e;
         }
       }
     }
+    if (e <= 9) id = pa;
+    else if (e <= 18) id = (uint64_t)pa * kPow10u[e - 9] + pb;
+    else id = ((uint64_t)pa * 1000000000ull + pb) * kPow10u[e - 18] + pc;
     uint32_t p = s + e;
     while (p < E && is_sep(buf[p])) ++p;
     const uint32_t k0 = p;
@@ -309,19 +318,31 @@ __global__ __launch_bounds__(kParseThreads) void k_text_parse(const uint8_t *tex
     } else if (E - k0 < 166) {
       kind = 4;
     } else {
-      // 168 characters from k0: the key field, its width, its bits
+      // 168 characters from k0: characters 0..163 (words 0..40) must all be
+      // '0'/'1'; word 41 (characters 164..167) sets the width.  Two words at a
+      // time become a byte of keys: the low bits of word i to bits 0..3, of
+      // word i + 1 to bits 4..7, gathered by one multiply (no two partial
+      // products meet, so nothing carries into the top byte).
+      bool all01 = true;
       uint32_t width = 168;
 #pragma unroll
-      for (uint32_t i = 0; i < 42; ++i) {
-        const uint32_t x = lds_u32(buf, k0 + 4 * i);
-        const uint32_t bad = not01_bytes(x);
-        if (bad && width == 168) width = 4 * i + ((uint32_t)__builtin_ctz(bad) >> 3);
-        const uint64_t nb = (uint64_t)nibble(x);
-        if (i < 16) w0 |= nb << (4 * i);
-        else if (i < 32) w1 |= nb << (4 * (i - 16));
-        else w2 |= nb << (4 * (i - 32));
+      for (uint32_t i = 0; i < 42; i += 2) {
+        const uint32_t x0 = lds_u32(buf, k0 + 4 * i), x1 = lds_u32(buf, k0 + 4 * i + 4);
+        all01 = all01 && (x0 & 0xFEFEFEFEu) == 0x30303030u;
+        if (i + 1 < 41) {
+          all01 = all01 && (x1 & 0xFEFEFEFEu) == 0x30303030u;
+        } else {
+          const uint32_t bad = not01_bytes(x1);
+          width = 164 + (bad ? ((uint32_t)__builtin_ctz(bad) >> 3) : 4u);
+        }
+        const uint32_t y = (x0 & 0x01010101u) | ((x1 & 0x01010101u) << 4);
+        const uint64_t byte = (uint64_t)((y * 0x01020408u) >> 24);
+        const uint32_t j = i / 2;  // byte j of the 168-bit field
+        if (j < 8) w0 |= byte << (8 * j);
+        else if (j < 16) w1 |= byte << (8 * (j - 8));
+        else w2 |= byte << (8 * (j - 16));
       }
-      if (width != 166 && width != 167) {
+      if (!all01 || (width != 166 && width != 167)) {
         kind = 4;
       } else {
         w2 &= (1ull << (width - 128)) - 1ull;  // characters past the field
