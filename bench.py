@@ -118,6 +118,21 @@ class Goldens:
         return hit_hash(h) == bytes(self.z["uneven_hash"][i])
 
 
+def cpu_ident():
+    """Family, model and stepping from /proc/cpuinfo (they name the exact part
+    when the model-name string is generic)."""
+    vals = {}
+    try:
+        for line in open("/proc/cpuinfo"):
+            k, _, v = line.partition(":")
+            k = k.strip()
+            if k in ("vendor_id", "cpu family", "model", "stepping") and k not in vals:
+                vals[k] = v.strip()
+    except OSError:
+        pass
+    return vals
+
+
 def cpu_model():
     try:
         out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
@@ -720,7 +735,7 @@ def cpu_baseline(lib_np, qs, args, fpsynth):
                                                          f"serial form, {el1:.1f}s"},
          "cluster1024": {"seconds": ecl, "sample": "clustering of the whole 1024-query batch "
                                                    "for counts 2..8 (oracle/cluster.py)"},
-         "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+         "cpu_model": cpu_model(), "cpu_ident": cpu_ident(), "host_cpus": os.cpu_count()}
     log("cpu:", json.dumps(r))
     return r
 
