@@ -402,6 +402,32 @@ def test_identical_rows(path):
     check_batch(words_lib(words), lib, qs, k, masks, path, "identical rows")
 
 
+@pytest.mark.parametrize("k,ties,fallback", [(1, 500, 0), (30, 1000, 0), (5, 1025, 0),
+                                              (40, 3000, 0), (30, 8192, None), (7, 8193, 1),
+                                              (2000, 0, 0)])
+def test_single_query_select_outcomes(k, ties, fallback):
+    """One query whose D_k-th distance is shared by `ties` records (planted
+    copies of the query): the select ranks up to 1,024 candidates with
+    d <= D_k directly, sorts 1,025..8,192 in LDS and leaves more to the exact
+    fallback (8,192 ties may also overflow the candidate buffer; the fallback
+    answers that too).  Every outcome equals the oracle's top-k."""
+    lib_np = fpsynth.make_library(60_000, 91)
+    words = lib_np.words.copy()
+    q = fpsynth.batch_queries(lib_np, 1, 92).words[0]
+    rng = np.random.default_rng(ties + k)
+    if ties:
+        words[rng.choice(len(words), ties, replace=False)] = q
+    say("case: single select outcome k", k, "ties", ties)
+    lib = fps.Library(words, strides=[0, 20_000, 60_000])
+    try:
+        got = lib.search(q, k)
+        assert np.array_equal(got, oracle.search(words, q, k))
+        if fallback is not None:
+            assert lib.last_stats()["fallbacks"] == fallback
+    finally:
+        lib.close()
+
+
 def words_lib(words):
     class W:
         pass
