@@ -69,6 +69,33 @@ __device__ __forceinline__ void expand_f4(const Rec1 &R, bool ok, uint8_t *buf,
   }
 }
 
+// Half of expand_f4 for blocks of 512 threads: thread tid takes record
+// tid & 255 and the fragments 3h .. 3h + 2 of it (h = tid >> 8); the |r| and
+// bias digits live in the last fragment.
+__device__ __forceinline__ void expand_half_f4(const Rec1 &R, bool ok, uint8_t *buf,
+                                               const uint32_t *poptab, uint32_t tid) {
+  const uint32_t rec = tid & 255u, h = tid >> 8;
+  const uint64_t ra = ok ? R.a : 0, rb = ok ? R.b : 0;
+  const uint32_t rc = ok ? R.c : 0, rd = ok ? R.d : 0;
+  const uint32_t ch[3] = {h ? (uint32_t)(rb >> 32) : (uint32_t)ra,
+                          h ? rc : (uint32_t)(ra >> 32), h ? rd : (uint32_t)rb};
+  uint32_t dw[12];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) spread_f4(ch[f], kDigitsRecord, dw + 4 * f);
+  if (h) {
+    const uint32_t pr = (uint32_t)(__popcll(ra) + __popcll(rb) + __popc(rc) + __popc(rd));
+    dw[11] = poptab[ok ? pr : 255u];
+    dw[8] |= kRecordBiasDw0;
+    dw[9] |= kRecordBiasDw1;
+  }
+  v4i_ *dst = reinterpret_cast<v4i_ *>(buf + rec * kF4Stride + 48 * h);
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    v4i_ v = {(int)dw[4 * f], (int)dw[4 * f + 1], (int)dw[4 * f + 2], (int)dw[4 * f + 3]};
+    dst[f] = v;
+  }
+}
+
 // A operands of a wave: lane holds query row row0 + mq * 32 + (lane & 31)
 // (K half lane >> 5), including the row's bias digits B = |q| - T - 1.
 template <int MQ>
@@ -246,24 +273,31 @@ __device__ __forceinline__ void stage_f4(const Workspace &ws, const QBlock &qb, 
 
 // COLS = false: the 4 waves hold different queries (128 * MQ per block).
 // COLS = true: the 4 waves share 32 * MQ queries and split the column blocks.
-template <int MQ, int WPE, bool COLS, int RING>
-__global__ __launch_bounds__(256, WPE) void k_scan_mfma_f4(Lib lib, Workspace ws, uint32_t nqb,
+// NW = 8: blocks of 8 waves (two per SIMD) share each stage's expansion,
+// each thread expanding half a record.
+template <int MQ, int WPE, bool COLS, int RING, int NW>
+__global__ __launch_bounds__(64 * NW, WPE) void k_scan_mfma_f4(Lib lib, Workspace ws, uint32_t nqb,
                                                            const uint64_t *item_off,
                                                            uint64_t tile_lo, uint64_t items,
                                                            uint64_t per_block) {
   constexpr int kRows = MQ * 32;  // query rows of a wave
   __shared__ __attribute__((aligned(16))) uint8_t lds[2][kSubF4 * kF4Stride];
   __shared__ uint32_t poptab[256];
-  __shared__ RowInfo h_row[4][kRows];
-  __shared__ uint32_t h_cnt[4][kRows], h_base[4][kRows], h_sbase[4][kRows];
-  __shared__ uint64_t h_list[4][kHitCap];
+  __shared__ RowInfo h_row[NW][kRows];
+  __shared__ uint32_t h_cnt[NW][kRows], h_base[NW][kRows], h_sbase[NW][kRows];
+  __shared__ uint64_t h_list[NW][kHitCap];
   const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const uint64_t it0 = (uint64_t)blockIdx.x * per_block;
   const uint64_t it1 = min(it0 + per_block, items);
   if (it0 >= it1) return;
   HitBuf hb{h_row[wv], h_cnt[wv], h_base[wv], h_sbase[wv], h_list[wv], 0};
   hits_init<kRows>(lane, h_cnt[wv]);
-  poptab[tid] = pop_digits(tid);
+  if (tid < 256) poptab[tid] = pop_digits(tid);
+  const uint32_t rtid = NW == 4 ? tid : (tid & 255u);  // the record this thread loads
+  auto expand = [&](const Rec1 &R, bool ok, uint8_t *buf) {
+    if constexpr (NW == 4) expand_f4(R, ok, buf, poptab, tid);
+    else expand_half_f4(R, ok, buf, poptab, tid);
+  };
   const uint64_t nst = (it1 - it0) * kStagesF4;
   const uint32_t row0 = COLS ? 0u : wv * (MQ * 32);
   v8i A[MQ][3];
@@ -290,16 +324,16 @@ __global__ __launch_bounds__(256, WPE) void k_scan_mfma_f4(Lib lib, Workspace ws
     return st;
   };
   Stage cs = next_stage();
-  const Rec1 first = load_rec1(lib, cs, tid);
+  const Rec1 first = load_rec1(lib, cs, rtid);
   Stage S[RING];
   Rec1 R[RING];
 #pragma unroll
   for (int j = 1; j <= RING; ++j) {
     S[j % RING] = next_stage();
-    R[j % RING] = load_rec1(lib, S[j % RING], tid);
+    R[j % RING] = load_rec1(lib, S[j % RING], rtid);
   }
   __syncthreads();  // poptab
-  expand_f4(first, cs.g0 + tid < cs.g1, lds[0], poptab, tid);
+  expand(first, cs.g0 + rtid < cs.g1, lds[0]);
   __syncthreads();
   // nst is a multiple of kStagesF4, hence of RING
   for (uint64_t s0 = 0; s0 < nst; s0 += RING) {
@@ -325,9 +359,9 @@ __global__ __launch_bounds__(256, WPE) void k_scan_mfma_f4(Lib lib, Workspace ws
         // the expansion gates the block's barrier: it goes ahead of the
         // products of the other waves on the SIMD
         __builtin_amdgcn_s_setprio(2);
-        expand_f4(R[nx], cn.g0 + tid < cn.g1, lds[(j + 1) & 1], poptab, tid);
+        expand(R[nx], cn.g0 + rtid < cn.g1, lds[(j + 1) & 1]);
         S[nx] = next_stage();
-        R[nx] = load_rec1(lib, S[nx], tid);
+        R[nx] = load_rec1(lib, S[nx], rtid);
         lds_barrier();
         __builtin_amdgcn_s_setprio(0);
         cs = cn;
@@ -342,13 +376,15 @@ __global__ __launch_bounds__(256, WPE) void k_scan_mfma_f4(Lib lib, Workspace ws
 //   1: 128 queries per wave, 512 per block
 //   2: 64 queries shared by the 4 waves, which split the columns (small batches)
 //   3: 32 queries per wave, 128 per block, two waves per SIMD
-int mfma_f4_variants() { return 4; }
+//   4: 64 queries per wave, 8 waves (512 queries) per block, one block per CU
+int mfma_f4_variants() { return 5; }
 
 uint32_t mfma_f4_qblock(int variant) {
   switch (variant) {
     case 1: return 4 * 4 * 32;
     case 2: return 2 * 32;
     case 3: return 4 * 1 * 32;
+    case 4: return 8 * 2 * 32;
     default: return 4 * 2 * 32;
   }
 }
@@ -357,20 +393,21 @@ void launch_scan_mfma_f4(const Lib &lib, const Workspace &ws, uint32_t nqb,
                          const uint64_t *item_off, uint64_t tile_lo, uint64_t items, int cus,
                          int variant, hipStream_t s, const LaunchEv &ev) {
   if (items == 0) return;
-  const int per_cu = variant == 1 ? 1 : 2;
+  const int per_cu = variant == 1 || variant == 4 ? 1 : 2;
   uint64_t blocks = (uint64_t)cus * per_cu;
   if (blocks > items) blocks = items;
   const uint64_t per = (items + blocks - 1) / blocks;
   blocks = (items + per - 1) / per;
-  const dim3 g((uint32_t)blocks), b(256);
-#define FPS_F4_LAUNCH(MQ, WPE, COLS, RING)                                                 \
-  launch_k((k_scan_mfma_f4<MQ, WPE, COLS, RING>), g, b, s, ev, lib, ws, nqb, item_off, tile_lo, \
-           items, per)
+  const dim3 g((uint32_t)blocks), b(256), b8(512);
+#define FPS_F4_LAUNCH(MQ, WPE, COLS, RING, NW)                                          \
+  launch_k((k_scan_mfma_f4<MQ, WPE, COLS, RING, NW>), g, NW == 8 ? b8 : b, s, ev, lib, ws, nqb, \
+           item_off, tile_lo, items, per)
   switch (variant) {
-    case 1: FPS_F4_LAUNCH(4, 1, false, 2); break;
-    case 2: FPS_F4_LAUNCH(2, 2, true, 4); break;
-    case 3: FPS_F4_LAUNCH(1, 2, false, 4); break;
-    default: FPS_F4_LAUNCH(2, 2, false, 4); break;
+    case 1: FPS_F4_LAUNCH(4, 1, false, 2, 4); break;
+    case 2: FPS_F4_LAUNCH(2, 2, true, 4, 4); break;
+    case 3: FPS_F4_LAUNCH(1, 2, false, 4, 4); break;
+    case 4: FPS_F4_LAUNCH(2, 1, false, 4, 8); break;
+    default: FPS_F4_LAUNCH(2, 2, false, 4, 4); break;
   }
 #undef FPS_F4_LAUNCH
 }

@@ -1030,16 +1030,23 @@ static std::vector<std::pair<fps_path, int>> tune_candidates(const Plan &P) {
 // allowed (a server's request path): the single-query scan for one or two
 // live queries, the fp4 matrix-core kernel otherwise -- its shape of 64
 // queries shared by a block's four waves up to 64 queries, 64 queries per
-// wave beyond.
-static void default_path(const Plan &P, fps_path *path, int *variant) {
+// wave beyond, and eight such waves per block from 512 queries.
+static uint64_t live_queries(const Plan &P) {
   uint64_t live = 0;
   for (const auto &qi : P.qinfo) live += qi.keff > 0;
+  return live;
+}
+
+static int default_f4_variant(uint64_t live) { return live <= 64 ? 2 : live >= 512 ? 4 : 0; }
+
+static void default_path(const Plan &P, fps_path *path, int *variant) {
+  const uint64_t live = live_queries(P);
   if (live <= 2) {
     *path = FPS_PATH_SINGLE;
     *variant = 0;
   } else {
     *path = FPS_PATH_MFMA_F4;
-    *variant = live <= 64 ? 2 : 0;
+    *variant = default_f4_variant(live);
   }
 }
 
@@ -1050,7 +1057,9 @@ static fps_status resolve_path(fps_library *lib, SearchCtx *ctx, Plan &P, fps_pa
     *path = requested != FPS_PATH_AUTO ? requested : lib->path;
     // default tile shapes: 64 queries per wave, two waves per SIMD
     const int nv = *path == FPS_PATH_MFMA_F4 ? mfma_f4_variants() : mfma_variants();
-    *variant = lib->variant >= 0 ? lib->variant % nv : (*path == FPS_PATH_MFMA_F4 ? 0 : 1);
+    *variant = lib->variant >= 0 ? lib->variant % nv
+               : *path == FPS_PATH_MFMA_F4 ? (default_f4_variant(live_queries(P)) == 4 ? 4 : 0)
+                                           : 1;
     return FPS_OK;
   }
   *variant = 0;

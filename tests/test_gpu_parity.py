@@ -86,7 +86,7 @@ def test_batch_paths_uneven_k_masks(small, path):
 
 
 @pytest.mark.parametrize("path,variant", [(fps.PATH_MFMA_I8, v) for v in range(5)] +
-                         [(fps.PATH_MFMA_F4, v) for v in range(4)])
+                         [(fps.PATH_MFMA_F4, v) for v in range(5)])
 def test_mfma_variants(small, path, variant):
     """Every matrix-core tile shape gives the oracle's answer (partial query
     blocks included: 600 queries over 3 masks)."""
