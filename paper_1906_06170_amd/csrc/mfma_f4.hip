@@ -278,8 +278,7 @@ __device__ __forceinline__ void stage_f4(const Workspace &ws, const QBlock &qb, 
 template <int MQ, int WPE, bool COLS, int RING, int NW>
 __global__ __launch_bounds__(64 * NW, WPE) void k_scan_mfma_f4(Lib lib, Workspace ws, uint32_t nqb,
                                                            const uint64_t *item_off,
-                                                           uint64_t tile_lo, uint64_t items,
-                                                           uint64_t per_block) {
+                                                           uint64_t tile_lo, uint64_t items) {
   constexpr int kRows = MQ * 32;  // query rows of a wave
   __shared__ __attribute__((aligned(16))) uint8_t lds[2][kSubF4 * kF4Stride];
   __shared__ uint32_t poptab[256];
@@ -287,9 +286,12 @@ __global__ __launch_bounds__(64 * NW, WPE) void k_scan_mfma_f4(Lib lib, Workspac
   __shared__ uint32_t h_cnt[NW][kRows], h_base[NW][kRows], h_sbase[NW][kRows];
   __shared__ uint64_t h_list[NW][kHitCap];
   const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const uint64_t it0 = (uint64_t)blockIdx.x * per_block;
-  const uint64_t it1 = min(it0 + per_block, items);
-  if (it0 >= it1) return;
+  // work items blockIdx.x, blockIdx.x + gridDim.x, ... (round robin: every
+  // block samples every query block, whatever its rows' k)
+  const uint64_t nit =
+      items > blockIdx.x ? (items - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
+  if (nit == 0) return;
+  auto item_of = [&](uint64_t j) { return (uint64_t)blockIdx.x + j * gridDim.x; };
   HitBuf hb{h_row[wv], h_cnt[wv], h_base[wv], h_sbase[wv], h_list[wv], 0};
   hits_init<kRows>(lane, h_cnt[wv]);
   if (tid < 256) poptab[tid] = pop_digits(tid);
@@ -298,7 +300,7 @@ __global__ __launch_bounds__(64 * NW, WPE) void k_scan_mfma_f4(Lib lib, Workspac
     if constexpr (NW == 4) expand_f4(R, ok, buf, poptab, tid);
     else expand_half_f4(R, ok, buf, poptab, tid);
   };
-  const uint64_t nst = (it1 - it0) * kStagesF4;
+  const uint64_t nst = nit * kStagesF4;
   const uint32_t row0 = COLS ? 0u : wv * (MQ * 32);
   v8i A[MQ][3];
   uint32_t a_qb = 0xFFFFFFFFu;
@@ -307,7 +309,7 @@ __global__ __launch_bounds__(64 * NW, WPE) void k_scan_mfma_f4(Lib lib, Workspac
 
   // loader: the next stage to load is tload, of work item litem
   uint64_t tload = 0;
-  Item litem = describe(ws, item_off, nqb, tile_lo, it0);
+  Item litem = describe(ws, item_off, nqb, tile_lo, item_of(0));
   // Past the last stage the loader yields empty stages (record 0 is read and
   // expanded as invalid), so that every stage issues the same loads: the
   // compiler can then count the loads in flight exactly and waits for each
@@ -317,7 +319,7 @@ __global__ __launch_bounds__(64 * NW, WPE) void k_scan_mfma_f4(Lib lib, Workspac
     if (tload < nst) {
       const uint32_t sub = (uint32_t)(tload % kStagesF4);
       if (sub == 0 && tload > 0)
-        litem = describe(ws, item_off, nqb, tile_lo, it0 + tload / kStagesF4);
+        litem = describe(ws, item_off, nqb, tile_lo, item_of(tload / kStagesF4));
       st = stage_of<kSubF4>(litem, sub);
     }
     ++tload;
@@ -396,12 +398,10 @@ void launch_scan_mfma_f4(const Lib &lib, const Workspace &ws, uint32_t nqb,
   const int per_cu = variant == 1 || variant == 4 ? 1 : 2;
   uint64_t blocks = (uint64_t)cus * per_cu;
   if (blocks > items) blocks = items;
-  const uint64_t per = (items + blocks - 1) / blocks;
-  blocks = (items + per - 1) / per;
   const dim3 g((uint32_t)blocks), b(256), b8(512);
 #define FPS_F4_LAUNCH(MQ, WPE, COLS, RING, NW)                                          \
   launch_k((k_scan_mfma_f4<MQ, WPE, COLS, RING, NW>), g, NW == 8 ? b8 : b, s, ev, lib, ws, nqb, \
-           item_off, tile_lo, items, per)
+           item_off, tile_lo, items)
   switch (variant) {
     case 1: FPS_F4_LAUNCH(4, 1, false, 2, 4); break;
     case 2: FPS_F4_LAUNCH(2, 2, true, 4, 4); break;

@@ -508,9 +508,13 @@ extern "C" fps_status fps_workspace_bytes(const fps_library *lib, uint32_t q, co
 
 // Groups queries by RangeSet into blocks of at most `qbs` queries; fills perm,
 // the blocks, and for every scan phase the prefix of work items (batch tiles of
-// the phase) over the blocks: items[p * (nblocks + 1) + b].
-void fps_make_blocks(Plan *P, uint32_t qbs, const std::vector<uint64_t> &tile_bounds,
-                     std::vector<QBlock> *blocks, std::vector<uint64_t> *items) {
+// the phase) over the blocks: items[p * (nblocks + 1) + b].  group_k: the rows
+// of a RangeSet in order of k (for a kernel whose blocks take the work items
+// round robin, so that blocks of candidate-heavy large-k rows do not set the
+// grid's tail).
+static void fps_make_blocks(Plan *P, uint32_t qbs, const std::vector<uint64_t> &tile_bounds,
+                            bool group_k, std::vector<QBlock> *blocks,
+                            std::vector<uint64_t> *items) {
   P->perm.clear();
   blocks->clear();
   for (uint32_t r = 0; r < P->rsets.size(); ++r) {
@@ -529,7 +533,7 @@ void fps_make_blocks(Plan *P, uint32_t qbs, const std::vector<uint64_t> &tile_bo
       std::stable_sort(sorted.begin(), sorted.end(), [&](uint32_t x, uint32_t y) {
         return P->qinfo[x].keff < P->qinfo[y].keff;
       });
-      const size_t n = sorted.size(), W = (n + 31) / 32;
+      const size_t n = sorted.size(), W = group_k ? 1 : (n + 31) / 32;
       size_t o = first;
       for (size_t g = 0; g < W; ++g)
         for (size_t j = g; j < n; j += W) P->perm[o++] = sorted[j];
@@ -640,11 +644,13 @@ static fps_status launch_search(fps_library *lib, SearchCtx *ctx, Plan &P, fps_p
   // blocks for the bound kernel and for the batched scan
   std::vector<QBlock> bblocks, qblocks;
   std::vector<uint64_t> bitems, qitems;
-  fps_make_blocks(&P, kBoundQBlock, tbb, &bblocks, &bitems);
+  // the fp4 kernel takes its work items round robin and its rows grouped by k
+  const bool group_k = path == FPS_PATH_MFMA_F4;
+  fps_make_blocks(&P, kBoundQBlock, tbb, group_k, &bblocks, &bitems);
   const uint32_t qbs = path == FPS_PATH_MFMA_I8   ? mfma_qblock(variant)
                        : path == FPS_PATH_MFMA_F4 ? mfma_f4_qblock(variant)
                                                   : (uint32_t)kPopQBlock;
-  fps_make_blocks(&P, qbs, tbb, &qblocks, &qitems);
+  fps_make_blocks(&P, qbs, tbb, group_k, &qblocks, &qitems);
   const uint32_t nqb = (uint32_t)qblocks.size();
   // parameter upload
   fps_status rc = ensure_pinned(&ctx->h_params, &ctx->h_params_bytes, P.params_bytes);
