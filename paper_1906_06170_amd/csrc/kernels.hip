@@ -319,8 +319,11 @@ __global__ __launch_bounds__(256) void k_scan_single(Lib lib, Workspace ws, uint
 void launch_scan_single(const Lib &lib, const Workspace &ws, uint32_t qidx, uint64_t t_begin,
                         uint64_t t_end, int cus, hipStream_t s, const LaunchEv &ev) {
   if (t_end <= t_begin) return;
+  // A wave per tile up to 256 blocks per CU (then grid-stride): the finer the
+  // grid, the shorter the tail; measured 2 % faster over 95.4 M records than
+  // 32 blocks per CU, and a resident grid (7 per CU) 5 % slower.
   uint64_t blocks = (t_end - t_begin + 3) / 4;  // 4 waves per block
-  const uint64_t maxb = (uint64_t)cus * 32;
+  const uint64_t maxb = (uint64_t)cus * 256;
   if (blocks > maxb) blocks = maxb;
   launch_k(k_scan_single, dim3((uint32_t)blocks), dim3(256), s, ev, lib, ws, qidx, t_begin, t_end);
 }
