@@ -405,7 +405,7 @@ __global__ __launch_bounds__(256) void k_wscan_mma(WLib L, WWs ws, const uint64_
   constexpr uint32_t RS = F::kRowStride;
   constexpr uint32_t QROW = F::kChunkBytes * (W / kWChunk);  // bytes per expanded query
   constexpr uint32_t NCH = W / kWChunk;
-  __shared__ __attribute__((aligned(16))) uint8_t bt[kWMmaRT * RS];
+  __shared__ __attribute__((aligned(16))) uint8_t bt[2][kWMmaRT * RS];
   __shared__ int32_t cq[kWMmaQB];   // |q| - T - 1 (large for rows past the block)
   __shared__ int32_t tq[kWMmaQB];   // T
   __shared__ uint32_t qid[kWMmaQB];
@@ -453,13 +453,24 @@ __global__ __launch_bounds__(256) void k_wscan_mma(WLib L, WWs ws, const uint64_
     uint32_t mypop = 0;
     uint64_t wa = rok ? L.w[(uint64_t)(2 * h) * L.np + g] : 0ull;
     uint64_t wb = rok ? L.w[(uint64_t)(2 * h + 1) * L.np + g] : 0ull;
+    // the wave's query fragments of a chunk, read one chunk ahead (they come
+    // from L2: read when needed they stalled every chunk's products)
+    const uint8_t *abase = arow + 16 * (lane >> 5);
+    wv4i Af[F::kSteps];
+    if (live) {
+#pragma unroll
+      for (uint32_t st = 0; st < F::kSteps; ++st)
+        Af[st] = *reinterpret_cast<const wv4i *>(abase + 32 * st);
+    }
+    // Chunk ch is expanded into bt[ch & 1] while the other buffer may still be
+    // read by the products of chunk ch - 1: one barrier per chunk.
     for (uint32_t ch = 0; ch < NCH; ++ch) {
       mypop += (uint32_t)(__popcll(wa) + __popcll(wb));
       // expand this thread's 128 keys of the chunk into the record's row
       {
         const uint32_t parts[4] = {(uint32_t)wa, (uint32_t)(wa >> 32), (uint32_t)wb,
                                    (uint32_t)(wb >> 32)};
-        uint8_t *dst = bt + rr * RS + h * (F::kChunkBytes / 2);
+        uint8_t *dst = bt[ch & 1] + rr * RS + h * (F::kChunkBytes / 2);
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
           uint32_t o[8];
@@ -480,19 +491,27 @@ __global__ __launch_bounds__(256) void k_wscan_mma(WLib L, WWs ws, const uint64_
       }
       __syncthreads();
       if (live) {
-        const uint8_t *ab = arow + ch * F::kChunkBytes + 16 * (lane >> 5);
+        wv4i An[F::kSteps];
+        if (ch + 1 < NCH) {
 #pragma unroll
-        for (uint32_t s = 0; s < F::kSteps; ++s) {
-          const wv4i a = *reinterpret_cast<const wv4i *>(ab + 32 * s);
+          for (uint32_t st = 0; st < F::kSteps; ++st)
+            An[st] = *reinterpret_cast<const wv4i *>(abase + (ch + 1) * F::kChunkBytes + 32 * st);
+        }
+        const uint8_t *bbuf = bt[ch & 1];
+#pragma unroll
+        for (uint32_t st = 0; st < F::kSteps; ++st) {
 #pragma unroll
           for (int ct = 0; ct < 4; ++ct) {
-            const wv4i bb = *reinterpret_cast<const wv4i *>(bt + (32 * ct + (lane & 31)) * RS +
-                                                             32 * s + 16 * (lane >> 5));
-            acc[ct] = F::mma(a, bb, acc[ct]);
+            const wv4i bb = *reinterpret_cast<const wv4i *>(bbuf + (32 * ct + (lane & 31)) * RS +
+                                                             32 * st + 16 * (lane >> 5));
+            acc[ct] = F::mma(Af[st], bb, acc[ct]);
           }
         }
+        if (ch + 1 < NCH) {
+#pragma unroll
+          for (uint32_t st = 0; st < F::kSteps; ++st) Af[st] = An[st];
+        }
       }
-      __syncthreads();
     }
     atomicAdd(&pr[rr], mypop);
     __syncthreads();
