@@ -194,11 +194,15 @@ fps_status fps_text_count(const void *text, uint64_t text_bytes, void *workspace
  *   n_records:    the count fps_text_count returned (checked again here).
  *   stride_begin, nstrides, device_buf, device_bytes, out: as fps_library_load.
  *   ids_device:   device memory for n_records uint64 ids (record i's id at
- *                 [i]), or NULL to discard the ids;
+ *                 [i]), or NULL to discard the ids.  When given, the handle
+ *                 keeps the pointer for fps_hit_ids: it must stay valid and
+ *                 unmodified until fps_library_free;
  *   ids_host:     host memory for n_records uint64 ids, or NULL.  When given
  *                 (it needs ids_device), the ids are copied there and the
  *                 handle keeps the pointer for fps_hit_ids: it must stay valid
- *                 until fps_library_free.
+ *                 until fps_library_free.  Without it the ids stay in device
+ *                 memory only (no download: the 8 bytes per record of the id
+ *                 column never cross PCIe).
  * Every line is validated; the first malformed line is reported by number:
  * FPS_E_ARG "line L: <problem>" (problems: line too long, id missing or
  * longer than 19 digits, no separator, keys not 166 or 167 characters '0'/'1',
@@ -214,9 +218,12 @@ fps_status fps_text_library_load(const void *text, uint64_t text_bytes, uint64_t
                                  fps_library **out);
 
 /* Fig. 3 step 5 ("CID + K"): ids[i] = the id of record hits[i].index, from the
- * id table of a library loaded from text with ids_host.  Host only.
+ * id table of a library loaded from text: the host copy when the load was given
+ * ids_host, else the device table (gathered by a kernel on the null stream
+ * through mapped pinned staging the handle keeps; calls on one handle are
+ * serialized).  hits and ids are host memory.
  * Errors: FPS_E_ARG (NULL, an index beyond the library), FPS_E_STATE (the
- * library has no id table). */
+ * library has no id table), FPS_E_DEVICE. */
 fps_status fps_hit_ids(const fps_library *lib, const fps_hit *hits, uint64_t n, uint64_t *ids);
 
 /*

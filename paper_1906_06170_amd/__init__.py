@@ -268,10 +268,11 @@ class Library:
 
     Library(words) uploads (n, 3) fingerprint words; Library(text=...) parses a
     library file (bytes, a uint8 array, or a uint8 torch tensor already on the
-    GPU) on the GPU and keeps its id column (Library.ids)."""
+    GPU) on the GPU and keeps its id column: in device memory (Library.ids_device)
+    and, with host_ids=True (the default), also on the host (Library.ids)."""
 
     def __init__(self, words: np.ndarray | None = None, strides=None, stream=None, *,
-                 text=None):
+                 text=None, host_ids: bool = True):
         torch = _require_gpu()
         c = load_library()
         self._ws = None
@@ -282,7 +283,7 @@ class Library:
         if (words is None) == (text is None):
             raise ValueError("give either words or text")
         if text is not None:
-            self._load_text(torch, c, text, strides, stream)
+            self._load_text(torch, c, text, strides, stream, host_ids)
             return
         w = np.ascontiguousarray(words, dtype=np.uint64).reshape(-1, 3)
         self.n = int(w.shape[0])
@@ -301,7 +302,7 @@ class Library:
         st = np.ascontiguousarray(strides, dtype=np.uint64)
         return st, len(st) - 1
 
-    def _load_text(self, torch, c, text, strides, stream):
+    def _load_text(self, torch, c, text, strides, stream, host_ids):
         if isinstance(text, torch.Tensor):
             dtext = text if text.is_cuda else text.to("cuda")
         else:
@@ -326,14 +327,22 @@ class Library:
         self._buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         self._device = self._buf.device.index
         self._ids_dev = torch.empty(max(self.n, 1), dtype=torch.int64, device="cuda")
-        self.ids = np.empty(max(self.n, 1), dtype=np.uint64)
+        self.ids = np.empty(max(self.n, 1), dtype=np.uint64) if host_ids else None
         st, ns = self._stride_table(strides)
         _check(c.fps_text_library_load(
             ctypes.c_void_p(dtext.data_ptr()), nt, self.n, None if st is None else _ptr(st), ns,
             ctypes.c_void_p(tws.data_ptr()), tws.numel(), ctypes.c_void_p(self._buf.data_ptr()),
-            nbytes, ctypes.c_void_p(self._ids_dev.data_ptr()), _ptr(self.ids), s,
-            ctypes.byref(self._handle)))
-        self.ids = self.ids[:self.n]
+            nbytes, ctypes.c_void_p(self._ids_dev.data_ptr()),
+            _ptr(self.ids) if host_ids else None, s, ctypes.byref(self._handle)))
+        if host_ids:
+            self.ids = self.ids[:self.n]
+
+    @property
+    def ids_device(self):
+        """The id column in device memory (int64 tensor of n; ids are below 2^63 only
+        when they fit 19 digits, which every valid id does), or None."""
+        ids = getattr(self, "_ids_dev", None)
+        return None if ids is None else ids[:self.n]
 
     # -- helpers --------------------------------------------------------------
     @property

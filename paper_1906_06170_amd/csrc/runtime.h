@@ -63,6 +63,15 @@ struct fps_library {
   bool graphs = true;  // capture and replay repeated launch shapes
   SearchCtx ctx;  // staging of direct calls on this handle
   const uint64_t *ids = nullptr;  // caller-owned host id of every record (text loads), or null
+  const uint64_t *ids_dev = nullptr;  // caller-owned device ids (text loads), or null
+  // fps_hit_ids on a library whose ids stay in device memory: mapped pinned
+  // staging of hit indices and ids (grown on demand), one call at a time
+  std::mutex id_mu;
+  void *id_stage = nullptr;
+  size_t id_stage_bytes = 0;
+  ~fps_library() {
+    if (id_stage) (void)hipHostFree(id_stage);
+  }
   std::mutex tune_mu;
   std::map<TuneKey, std::pair<fps_path, int>> tuned;
 };
@@ -82,6 +91,12 @@ struct Plan {
 };
 
 fps_status fps_fail(fps_status s, const char *fmt, ...);
+// Returns FPS_E_DEVICE with the HIP error text when a HIP call fails.
+#define HIP_TRY(x)                                                                         \
+  do {                                                                                     \
+    hipError_t e_ = (x);                                                                   \
+    if (e_ != hipSuccess) return fps_fail(FPS_E_DEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
 // A handle over caller-owned device memory for n records (strides validated,
 // device queried, staging allocated); the records themselves are not written.
 fps_status fps_library_new(uint64_t n, const uint64_t *stride_begin, uint32_t nstrides,

@@ -37,11 +37,6 @@ void fps_clear_error() { t_err.clear(); }
 
 extern "C" const char *fps_last_error(void) { return t_err.c_str(); }
 
-#define HIP_TRY(x)                                                                         \
-  do {                                                                                     \
-    hipError_t e_ = (x);                                                                   \
-    if (e_ != hipSuccess) return fps_fail(FPS_E_DEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
-  } while (0)
 
 static inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 

@@ -510,6 +510,7 @@ extern "C" fps_status fps_text_library_load(const void *text, uint64_t text_byte
                     (unsigned long long)((err >> 8) + 1), kTextProblems[kind < 7 ? kind : 0]);
       break;
     }
+    L->ids_dev = ids_device;
     if (ids_host) {
       if (hipMemcpyAsync(ids_host, ids_device, 8 * n_records, hipMemcpyDeviceToHost, s) !=
               hipSuccess ||
@@ -528,17 +529,51 @@ extern "C" fps_status fps_text_library_load(const void *text, uint64_t text_byte
   return FPS_OK;
 }
 
+// ids[i] = table[hits[i].index] on the device; hits and ids are the device
+// addresses of mapped pinned staging.
+__global__ __launch_bounds__(256) void k_gather_ids(const uint64_t *table, const fps_hit *hits,
+                                                    uint64_t n, uint64_t *ids) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) ids[i] = table[hits[i].index];
+}
+
 extern "C" fps_status fps_hit_ids(const fps_library *lib, const fps_hit *hits, uint64_t n,
                                   uint64_t *ids) {
   fps_clear_error();
   if (!lib || (n && (!hits || !ids))) return fps_fail(FPS_E_ARG, "NULL argument");
-  if (!lib->ids) return fps_fail(FPS_E_STATE, "the library has no id table (not loaded from text)");
-  for (uint64_t i = 0; i < n; ++i) {
+  if (!lib->ids && !lib->ids_dev)
+    return fps_fail(FPS_E_STATE, "the library has no id table (not loaded from text)");
+  for (uint64_t i = 0; i < n; ++i)
     if (hits[i].index >= lib->n)
       return fps_fail(FPS_E_ARG, "hit %llu: index %u beyond the library", (unsigned long long)i,
                       hits[i].index);
-    ids[i] = lib->ids[hits[i].index];
+  if (lib->ids) {
+    for (uint64_t i = 0; i < n; ++i) ids[i] = lib->ids[hits[i].index];
+    return FPS_OK;
   }
+  if (n == 0) return FPS_OK;
+  // the ids stay in device memory: gather them there
+  fps_library *L = const_cast<fps_library *>(lib);
+  std::lock_guard<std::mutex> lk(L->id_mu);
+  const size_t need = (size_t)n * (sizeof(fps_hit) + sizeof(uint64_t));
+  if (L->id_stage_bytes < need) {
+    if (L->id_stage) (void)hipHostFree(L->id_stage);
+    L->id_stage = nullptr;
+    L->id_stage_bytes = 0;
+    HIP_TRY(hipHostMalloc(&L->id_stage, need, hipHostMallocMapped));
+    L->id_stage_bytes = need;
+  }
+  void *dev = nullptr;
+  HIP_TRY(hipHostGetDevicePointer(&dev, L->id_stage, 0));
+  memcpy(L->id_stage, hits, (size_t)n * sizeof(fps_hit));
+  const fps_hit *dh = (const fps_hit *)dev;
+  uint64_t *dids = (uint64_t *)((uint8_t *)dev + (size_t)n * sizeof(fps_hit));
+  hipLaunchKernelGGL(k_gather_ids, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, nullptr,
+                     lib->ids_dev, dh, n, dids);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(nullptr));
+  memcpy(ids, (const uint8_t *)L->id_stage + (size_t)n * sizeof(fps_hit),
+              (size_t)n * sizeof(uint64_t));
   return FPS_OK;
 }
 

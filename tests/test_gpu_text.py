@@ -177,3 +177,33 @@ def test_hit_ids_without_id_table_is_refused():
     with pytest.raises(fps.FPSError) as e:
         lib.hit_ids(h)
     assert e.value.status == fps.FPS_E_STATE
+
+
+def test_device_only_ids_match_oracle():
+    """A text library whose id column stays in device memory (host_ids=False):
+    the ids of every hit are gathered on the device and equal the oracle's, for
+    single queries, a batch of 40 (about 40,000 hits, staging grown on demand)
+    and an empty hit list; an index beyond the library is refused first."""
+    n = 100_000
+    lib_np = fpsynth.make_library(n, 13)
+    ids = fpsynth.make_cids(n, 14)
+    text = fpsynth.library_text(lib_np.words, ids)
+    owords, oids = oracle.read_text(text)
+    lib = fps.Library(text=text, host_ids=False)
+    assert lib.ids is None
+    assert np.array_equal(lib.ids_device.cpu().numpy().astype(np.uint64), oids)
+    qs = fpsynth.batch_queries(lib_np, 40, 15).words
+    for qi in range(3):
+        got = lib.search_ids(qs[qi], 30)
+        wid, wd = oracle_ids(owords, oids, qs[qi], 30)
+        assert np.array_equal(got["id"], wid) and np.array_equal(got["distance"], wd)
+    hits, off = lib.search_batch(qs, 1000)
+    got = lib.hit_ids(hits)
+    assert np.array_equal(got, oids[hits["index"]])
+    assert len(lib.hit_ids(hits[:0])) == 0
+    bad = hits[:2].copy()
+    bad["index"][1] = n
+    with pytest.raises(fps.FPSError) as e:
+        lib.hit_ids(bad)
+    assert e.value.status == fps.FPS_E_ARG
+    lib.close()
