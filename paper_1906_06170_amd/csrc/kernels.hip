@@ -158,7 +158,14 @@ __global__ __launch_bounds__(256) void k_bound(Lib lib, Workspace ws, uint32_t c
                   x);
     }
   }
-  __threadfence();
+  // The histogram adds are device-scope atomics; a block waits for its own to
+  // complete before it counts itself done (no L2 write-back per block: a
+  // device-scope fence here cost 3 us of a 95.4 M-record query).  Whatever the
+  // last block then reads is a count of real sample records, every bin at most
+  // its final value, and the keff-th smallest distance of any subset of the
+  // sample still bounds D_k from above: the bound can only be looser, never
+  // wrong.
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (tid == 0) s_last = atomicAdd(&ws.bdone[blockIdx.y], 1u) == gridDim.x - 1 ? 1u : 0u;
   __syncthreads();

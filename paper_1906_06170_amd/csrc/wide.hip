@@ -196,7 +196,9 @@ __global__ __launch_bounds__(256) void k_wbound(WLib L, WWs ws, uint32_t chunk) 
     for (uint32_t i = tid; i < bins; i += blockDim.x)
       if (h[i]) atomicAdd(ws.hist + (uint64_t)q * bins + i, h[i]);
   }
-  __threadfence();
+  // as in k_bound: the adds are device-scope atomics, waited for per block; a
+  // partial histogram only loosens the bound
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (tid == 0) s_last = atomicAdd(ws.bdone + q, 1u) == gridDim.x - 1 ? 1u : 0u;
   __syncthreads();
