@@ -141,9 +141,11 @@ fps_status fps_set_timing(fps_library *lib, int enable);
  * per SIMD, 2 = 128 per wave, 3 = 32 per wave with two waves per SIMD, 4 = 64
  * queries shared by a block's four waves, which split the records.  fp4: 0 = 64
  * queries per wave with two waves per SIMD, 1 = 128 per wave, 2 = 64 queries
- * shared by the four waves, 3 = 32 per wave with two waves per SIMD.  A value
- * beyond the path's shapes wraps around.  -1 (default): the autotuner chooses
- * under FPS_PATH_AUTO; a forced path takes int8 shape 1 or fp4 shape 0.
+ * shared by the four waves, 3 = 32 per wave with two waves per SIMD, 4 = 64
+ * queries per wave in blocks of eight waves (512 queries).  A value beyond the
+ * path's shapes wraps around.  -1 (default): the autotuner chooses under
+ * FPS_PATH_AUTO; a forced path takes int8 shape 1, or fp4 shape 4 for 512 or
+ * more live queries and shape 0 below.
  * Results never depend on it.  Errors: FPS_E_ARG (variant < -1 or >= 5). */
 fps_status fps_set_variant(fps_library *lib, int variant);
 
