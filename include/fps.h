@@ -205,6 +205,10 @@ fps_status fps_text_count(const void *text, uint64_t text_bytes, void *workspace
  *                 until fps_library_free.  Without it the ids stay in device
  *                 memory only (no download: the 8 bytes per record of the id
  *                 column never cross PCIe).
+ * When workspace still holds what fps_text_count computed for this text
+ * (same address and size) and n_records, the lines are not counted again; the
+ * parse checks every chunk's newlines against those counts (FPS_E_ARG "line L:
+ * the text changed since it was counted" if they differ).
  * Every line is validated; the first malformed line is reported by number:
  * FPS_E_ARG "line L: <problem>" (problems: line too long, id missing or
  * longer than 19 digits, no separator, keys not 166 or 167 characters '0'/'1',

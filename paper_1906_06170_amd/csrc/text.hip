@@ -267,6 +267,10 @@ __global__ __launch_bounds__(kParseThreads) void k_text_parse(const uint8_t *tex
     }
   }
   __syncthreads();
+  // the chunk's newlines must be the ones counted (a text changed between its
+  // count and this parse would otherwise place lines silently wrong)
+  if (tid == 0 && nl_before[blockIdx.x + 1] - nl_before[blockIdx.x] != total)
+    atomicMin(o.err, (unsigned long long)(((blockIdx.x ? nl_before[blockIdx.x] + 1 : 0) << 8) | 7u));
   // the lines of this chunk
   const bool first = blockIdx.x == 0;
   const uint64_t text_end = bytes - base;  // chunk-relative end of the text
@@ -404,6 +408,7 @@ struct TextWs {
   uint64_t *before;  // nchunks prefix entries, then newlines, then records
   uint64_t *tiles;
   unsigned long long *err;
+  uint64_t *tag;     // text address, text bytes, records of the last count
 };
 
 static fps_status text_validate(const void *text, uint64_t text_bytes, void *workspace,
@@ -424,6 +429,7 @@ static fps_status text_validate(const void *text, uint64_t text_bytes, void *wor
   t->before = (uint64_t *)(p + align256(4 * nc));
   t->tiles = (uint64_t *)(p + align256(4 * nc) + align256(8 * (nc + 2)));
   t->err = (unsigned long long *)((uint8_t *)t->tiles + align256(8 * text_tiles(nc)));
+  t->tag = (uint64_t *)(t->err + 1);
   return FPS_OK;
 }
 
@@ -454,13 +460,22 @@ extern "C" fps_status fps_text_count(const void *text, uint64_t text_bytes, void
   TextWs t;
   fps_status rc = text_validate(text, text_bytes, workspace, ws_bytes, &t);
   if (rc) return rc;
-  return text_lines((const uint8_t *)text, text_bytes, t, (hipStream_t)stream, n_records);
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = text_lines((const uint8_t *)text, text_bytes, t, s, n_records))) return rc;
+  // remember which text these counts belong to: a load of the same text with
+  // this workspace need not count again
+  const uint64_t tag[3] = {(uint64_t)(uintptr_t)text, text_bytes, *n_records};
+  if (hipMemcpyAsync(t.tag, tag, sizeof tag, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fps_fail(FPS_E_DEVICE, "text count tag failed");
+  return FPS_OK;
 }
 
 static const char *const kTextProblems[] = {
     "", "line longer than 255 characters", "id missing or longer than 19 digits",
     "no separator after the id", "keys not 166 or 167 characters 0/1",
-    "position 0 set (it holds no key)", "characters other than blanks after the keys"};
+    "position 0 set (it holds no key)", "characters other than blanks after the keys",
+    "the text changed since it was counted"};
 
 extern "C" fps_status fps_text_library_load(const void *text, uint64_t text_bytes,
                                             uint64_t n_records, const uint64_t *stride_begin,
@@ -478,7 +493,15 @@ extern "C" fps_status fps_text_library_load(const void *text, uint64_t text_byte
   hipStream_t s = (hipStream_t)stream;
   const uint8_t *tx = (const uint8_t *)text;
   uint64_t lines = 0;
-  if ((rc = text_lines(tx, text_bytes, t, s, &lines))) return rc;
+  uint64_t tag[3] = {0, 0, 0};
+  if (hipMemcpyAsync(tag, t.tag, sizeof tag, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fps_fail(FPS_E_DEVICE, "text count tag read failed");
+  if (tag[0] == (uint64_t)(uintptr_t)text && tag[1] == text_bytes && tag[2] == n_records) {
+    lines = n_records;  // counted by fps_text_count on this text; the parse checks every chunk
+  } else if ((rc = text_lines(tx, text_bytes, t, s, &lines))) {
+    return rc;
+  }
   if (lines != n_records)
     return fps_fail(FPS_E_ARG, "the text holds %llu lines, n_records = %llu",
                     (unsigned long long)lines, (unsigned long long)n_records);
@@ -507,7 +530,7 @@ extern "C" fps_status fps_text_library_load(const void *text, uint64_t text_byte
     if (err != ~0ull) {
       const uint32_t kind = (uint32_t)(err & 0xFF);
       rc = fps_fail(kind == 5 ? FPS_E_FINGERPRINT : FPS_E_ARG, "line %llu: %s",
-                    (unsigned long long)((err >> 8) + 1), kTextProblems[kind < 7 ? kind : 0]);
+                    (unsigned long long)((err >> 8) + 1), kTextProblems[kind < 8 ? kind : 0]);
       break;
     }
     L->ids_dev = ids_device;

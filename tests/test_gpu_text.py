@@ -207,3 +207,71 @@ def test_device_only_ids_match_oracle():
         lib.hit_ids(bad)
     assert e.value.status == fps.FPS_E_ARG
     lib.close()
+
+
+def test_counts_reused_and_changed_text_detected():
+    """fps_text_library_load reuses the counts fps_text_count left in the
+    workspace for the same text; a text whose lines moved across a chunk
+    boundary between the two calls is refused ("the text changed since it was
+    counted") instead of being parsed into wrong rows; counted again, the same
+    text gets the ordinary validation (its split line is malformed)."""
+    import ctypes
+    n = 40_000
+    lib_np = fpsynth.make_library(n, 21)
+    ids = fpsynth.make_cids(n, 22)
+    text = fpsynth.library_text(lib_np.words, ids)
+    c = fps.load_library()
+    dtext = torch.from_numpy(np.frombuffer(bytes(text), dtype=np.uint8).copy()).to("cuda")
+    nt = int(dtext.numel())
+    wsb = ctypes.c_size_t()
+    assert c.fps_text_workspace_bytes(nt, ctypes.byref(wsb)) == fps.FPS_OK
+    tws = torch.empty(int(wsb.value), dtype=torch.uint8, device="cuda")
+    cnt = ctypes.c_uint64()
+
+    def count():
+        assert c.fps_text_count(ctypes.c_void_p(dtext.data_ptr()), nt,
+                                ctypes.c_void_p(tws.data_ptr()), tws.numel(), None,
+                                ctypes.byref(cnt)) == fps.FPS_OK
+        return int(cnt.value)
+
+    def load(nrec):
+        nbytes = int(c.fps_library_device_bytes(nrec))
+        buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        idd = torch.empty(nrec, dtype=torch.int64, device="cuda")
+        h = ctypes.c_void_p()
+        rc = c.fps_text_library_load(ctypes.c_void_p(dtext.data_ptr()), nt, nrec, None, 0,
+                                     ctypes.c_void_p(tws.data_ptr()), tws.numel(),
+                                     ctypes.c_void_p(buf.data_ptr()), nbytes,
+                                     ctypes.c_void_p(idd.data_ptr()), None, None, ctypes.byref(h))
+        msg = c.fps_last_error().decode() if rc else ""
+        if rc == fps.FPS_OK:
+            c.fps_library_free(h)
+        return rc, msg, buf, idd
+
+    assert count() == n
+    rc, _, buf, idd = load(n)
+    assert rc == fps.FPS_OK
+    assert np.array_equal(idd.cpu().numpy().astype(np.uint64), ids)
+    ref = fps.Library(lib_np.words)
+    assert torch.equal(buf, ref._buf)
+    ref.close()
+    # the line that straddles the boundary of chunks 99 and 100 (16,384 bytes
+    # each) ends one character after its id instead: its newline moves into
+    # chunk 99, the line count stays n
+    host = dtext.cpu().numpy()
+    nls = np.nonzero(host == 10)[0]
+    boundary = 100 * 16384
+    L = int(np.searchsorted(nls, boundary))  # first newline at or past the boundary
+    start = int(nls[L - 1]) + 1
+    sep = start + int(np.nonzero(host[start:nls[L]] == 32)[0][0])
+    assert sep < boundary <= int(nls[L])
+    host[int(nls[L])] = 32
+    host[sep] = 10
+    dtext.copy_(torch.from_numpy(host).to("cuda"))
+    rc, msg, _, _ = load(n)
+    say("changed text:", msg)
+    assert rc == fps.FPS_E_ARG and "changed since it was counted" in msg
+    assert count() == n
+    rc, msg, _, _ = load(n)
+    say("counted again:", msg)
+    assert rc == fps.FPS_E_ARG and "changed" not in msg and msg.startswith("line ")
