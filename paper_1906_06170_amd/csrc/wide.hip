@@ -425,7 +425,7 @@ __global__ __launch_bounds__(256) void k_wexpand(WWs ws, uint32_t q) {
 }
 
 template <int W, int FMT>
-__global__ __launch_bounds__(256) void k_wscan_mma(WLib L, WWs ws, const uint64_t *item_off,
+__global__ __launch_bounds__(256, 2) void k_wscan_mma(WLib L, WWs ws, const uint64_t *item_off,
                                                    uint64_t vb, uint64_t ve, uint64_t items) {
   typedef MmaFmt<FMT> F;
   constexpr uint32_t RS = F::kRowStride;
@@ -477,20 +477,44 @@ __global__ __launch_bounds__(256) void k_wscan_mma(WLib L, WWs ws, const uint64_
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) acc[ct] = typename F::Acc{};
     uint32_t mypop = 0;
-    uint64_t wa = rok ? L.w[(uint64_t)(2 * h) * L.np + g] : 0ull;
-    uint64_t wb = rok ? L.w[(uint64_t)(2 * h + 1) * L.np + g] : 0ull;
+    // this thread's words of every chunk, requested at once: one memory
+    // latency per item (requested a chunk ahead, the loads left two blocks
+    // per CU with 16 bytes in flight per thread, about 1 TB/s at the chip's
+    // latency)
+    uint64_t wr[NCH][2];
+#pragma unroll
+    for (uint32_t ch = 0; ch < NCH; ++ch) {
+      const uint64_t k0 = (uint64_t)kWChunk * ch + 2 * h;
+      wr[ch][0] = rok ? L.w[k0 * L.np + g] : 0ull;
+      wr[ch][1] = rok ? L.w[(k0 + 1) * L.np + g] : 0ull;
+    }
     // the wave's query fragments of a chunk, read one chunk ahead (they come
     // from L2: read when needed they stalled every chunk's products)
     const uint8_t *abase = arow + 16 * (lane >> 5);
-    wv4i Af[F::kSteps];
-    if (live) {
+    // two register sets named statically (the chunk loop is unrolled): chunk
+    // ch multiplies with Ab[ch & 1] while Ab[(ch + 1) & 1] is being loaded (a
+    // copy from one set into the other made every chunk wait for the loads it
+    // had just issued)
+    // (every wave loads them, unconditionally: arow is a valid query row
+    // also for rows past the block, and loads under a branch made the
+    // compiler's wait counts assume the worst)
+    wv4i Ab[2][F::kSteps];
 #pragma unroll
-      for (uint32_t st = 0; st < F::kSteps; ++st)
-        Af[st] = *reinterpret_cast<const wv4i *>(abase + 32 * st);
-    }
+    for (uint32_t st = 0; st < F::kSteps; ++st)
+      Ab[0][st] = *reinterpret_cast<const wv4i *>(abase + 32 * st);
     // Chunk ch is expanded into bt[ch & 1] while the other buffer may still be
     // read by the products of chunk ch - 1: one barrier per chunk.
+#pragma unroll
     for (uint32_t ch = 0; ch < NCH; ++ch) {
+      // the next chunk's query fragments, requested before this chunk's
+      // barrier so that a whole chunk of work covers their latency
+      if (ch + 1 < NCH) {
+#pragma unroll
+        for (uint32_t st = 0; st < F::kSteps; ++st)
+          Ab[(ch + 1) & 1][st] =
+              *reinterpret_cast<const wv4i *>(abase + (ch + 1) * F::kChunkBytes + 32 * st);
+      }
+      const uint64_t wa = wr[ch][0], wb = wr[ch][1];
       mypop += (uint32_t)(__popcll(wa) + __popcll(wb));
       // expand this thread's 128 keys of the chunk into the record's row
       {
@@ -509,20 +533,8 @@ __global__ __launch_bounds__(256) void k_wscan_mma(WLib L, WWs ws, const uint64_
           }
         }
       }
-      // prefetch the next chunk's words
-      if (ch + 1 < NCH) {
-        const uint64_t k0 = (uint64_t)kWChunk * (ch + 1) + 2 * h;
-        wa = rok ? L.w[k0 * L.np + g] : 0ull;
-        wb = rok ? L.w[(k0 + 1) * L.np + g] : 0ull;
-      }
       __syncthreads();
       if (live) {
-        wv4i An[F::kSteps];
-        if (ch + 1 < NCH) {
-#pragma unroll
-          for (uint32_t st = 0; st < F::kSteps; ++st)
-            An[st] = *reinterpret_cast<const wv4i *>(abase + (ch + 1) * F::kChunkBytes + 32 * st);
-        }
         const uint8_t *bbuf = bt[ch & 1];
 #pragma unroll
         for (uint32_t st = 0; st < F::kSteps; ++st) {
@@ -530,12 +542,8 @@ __global__ __launch_bounds__(256) void k_wscan_mma(WLib L, WWs ws, const uint64_
           for (int ct = 0; ct < 4; ++ct) {
             const wv4i bb = *reinterpret_cast<const wv4i *>(bbuf + (32 * ct + (lane & 31)) * RS +
                                                              32 * st + 16 * (lane >> 5));
-            acc[ct] = F::mma(Af[st], bb, acc[ct]);
+            acc[ct] = F::mma(Ab[ch & 1][st], bb, acc[ct]);
           }
-        }
-        if (ch + 1 < NCH) {
-#pragma unroll
-          for (uint32_t st = 0; st < F::kSteps; ++st) Af[st] = An[st];
         }
       }
     }
