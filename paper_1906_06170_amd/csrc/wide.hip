@@ -60,6 +60,8 @@ struct WRange {
   uint64_t begin[FPS_MAX_STRIDES], end[FPS_MAX_STRIDES], voff[FPS_MAX_STRIDES + 1];
 };
 
+static_assert(sizeof(WRange) % 8 == 0, "copied into LDS as 64-bit words");
+
 struct WQuery {
   uint64_t cand_off, out_off, sample;
   uint32_t keff, cap, rset, popc;
@@ -431,21 +433,39 @@ __global__ __launch_bounds__(256, 2) void k_wscan_mma(WLib L, WWs ws, const uint
   constexpr uint32_t RS = F::kRowStride;
   constexpr uint32_t QROW = F::kChunkBytes * (W / kWChunk);  // bytes per expanded query
   constexpr uint32_t NCH = W / kWChunk;
+  // A wave multiplies QT query tiles by CT record tiles of 32 x 32: 1 x 4.
+  // (2 x 2 halves the LDS reads per product but doubles the query fragments
+  // every wave reads from L2, and measured 1.5x slower.)
+  constexpr int QT = 1, CT = 4 / QT;
   __shared__ __attribute__((aligned(16))) uint8_t bt[2][kWMmaRT * RS];
   __shared__ int32_t cq[kWMmaQB];   // |q| - T - 1 (large for rows past the block)
   __shared__ int32_t tq[kWMmaQB];   // T
   __shared__ uint32_t qid[kWMmaQB];
   __shared__ uint32_t pr[kWMmaRT];  // |r|
+  __shared__ WRange srs;            // the range set of the current query block
   const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  uint32_t cur = 0xFFFFFFFFu;
+  // The query block of an item, its first item and the range set are looked
+  // up when the block's items (in increasing order) enter a new query block:
+  // looked up per item, their chain of dependent global loads delayed every
+  // item's record loads by several microseconds.
+  uint32_t cur = 0xFFFFFFFFu, b = 0;
+  uint64_t bfirst = 0, bnext = ws.nqb > 1 ? item_off[1] : ~0ull;
   WBlock qb{};
   for (uint64_t item = blockIdx.x; item < items; item += gridDim.x) {
-    uint32_t b = 0;
-    while (b + 1 < ws.nqb && item >= item_off[b + 1]) ++b;
+    while (item >= bnext) {
+      ++b;
+      bfirst = bnext;
+      bnext = b + 1 < ws.nqb ? item_off[b + 1] : ~0ull;
+    }
     __syncthreads();
     if (b != cur) {
       cur = b;
       qb = ws.qb[b];
+      {
+        const uint64_t *src = reinterpret_cast<const uint64_t *>(ws.rs + qb.rset);
+        uint64_t *dst = reinterpret_cast<uint64_t *>(&srs);
+        for (uint32_t j = tid; j < sizeof(WRange) / 8; j += blockDim.x) dst[j] = src[j];
+      }
       for (uint32_t j = tid; j < kWMmaQB; j += blockDim.x) {
         if (j < qb.count) {
           const uint32_t q = ws.perm[qb.first + j];
@@ -461,36 +481,45 @@ __global__ __launch_bounds__(256, 2) void k_wscan_mma(WLib L, WWs ws, const uint
     }
     if (tid < kWMmaRT) pr[tid] = 0;
     __syncthreads();
-    const WRange *rs = ws.rs + qb.rset;
+    const WRange *rs = &srs;
     const uint64_t vend = min(ve, rs->neff);
-    const uint64_t v0 = vb + (item - item_off[b]) * kWMmaRT;
+    const uint64_t v0 = vb + (item - bfirst) * kWMmaRT;
     // thread: record rr, half h of every chunk (words 2h, 2h + 1 of it)
     const uint32_t rr = tid & (kWMmaRT - 1), h = tid >> 7;
     const uint64_t vr = v0 + rr;
     const bool rok = vr < vend;
     const uint64_t g = rok ? wv2g(rs, vr) : 0;
-    // the wave's query rows: 32 wv + (lane & 31)
-    const uint32_t row = 32 * wv + (lane & 31);
-    const bool live = 32 * wv < qb.count;
-    const uint8_t *arow = ws.qx + (uint64_t)qid[row < kWMmaQB ? row : 0] * QROW;
-    typename F::Acc acc[4];
+    // the wave's tiles: query tiles QT qg + mq, record tiles CT rg + ct
+    const uint32_t qg = wv / (4 / CT), rg = wv % (4 / CT);
+    const bool live = 32 * QT * qg < qb.count;
+    typename F::Acc acc[QT][CT];
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) acc[ct] = typename F::Acc{};
+    for (int mq = 0; mq < QT; ++mq)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) acc[mq][ct] = typename F::Acc{};
     uint32_t mypop = 0;
     // this thread's words of every chunk, requested at once: one memory
     // latency per item (requested a chunk ahead, the loads left two blocks
     // per CU with 16 bytes in flight per thread, about 1 TB/s at the chip's
     // latency)
+    // (loaded unconditionally, from record 0 past the range, and then
+    // cleared: sixteen branches around the loads also left the compiler's
+    // wait counts at their worst case)
     uint64_t wr[NCH][2];
 #pragma unroll
     for (uint32_t ch = 0; ch < NCH; ++ch) {
       const uint64_t k0 = (uint64_t)kWChunk * ch + 2 * h;
-      wr[ch][0] = rok ? L.w[k0 * L.np + g] : 0ull;
-      wr[ch][1] = rok ? L.w[(k0 + 1) * L.np + g] : 0ull;
+      const uint64_t x0 = L.w[k0 * L.np + g], x1 = L.w[(k0 + 1) * L.np + g];
+      wr[ch][0] = rok ? x0 : 0ull;
+      wr[ch][1] = rok ? x1 : 0ull;
     }
     // the wave's query fragments of a chunk, read one chunk ahead (they come
     // from L2: read when needed they stalled every chunk's products)
-    const uint8_t *abase = arow + 16 * (lane >> 5);
+    const uint8_t *abase[QT];
+#pragma unroll
+    for (int mq = 0; mq < QT; ++mq)
+      abase[mq] = ws.qx + (uint64_t)qid[32 * (QT * qg + mq) + (lane & 31)] * QROW +
+                  16 * (lane >> 5);
     // two register sets named statically (the chunk loop is unrolled): chunk
     // ch multiplies with Ab[ch & 1] while Ab[(ch + 1) & 1] is being loaded (a
     // copy from one set into the other made every chunk wait for the loads it
@@ -498,10 +527,12 @@ __global__ __launch_bounds__(256, 2) void k_wscan_mma(WLib L, WWs ws, const uint
     // (every wave loads them, unconditionally: arow is a valid query row
     // also for rows past the block, and loads under a branch made the
     // compiler's wait counts assume the worst)
-    wv4i Ab[2][F::kSteps];
+    wv4i Ab[2][QT][F::kSteps];
 #pragma unroll
-    for (uint32_t st = 0; st < F::kSteps; ++st)
-      Ab[0][st] = *reinterpret_cast<const wv4i *>(abase + 32 * st);
+    for (int mq = 0; mq < QT; ++mq)
+#pragma unroll
+      for (uint32_t st = 0; st < F::kSteps; ++st)
+        Ab[0][mq][st] = *reinterpret_cast<const wv4i *>(abase[mq] + 32 * st);
     // Chunk ch is expanded into bt[ch & 1] while the other buffer may still be
     // read by the products of chunk ch - 1: one barrier per chunk.
 #pragma unroll
@@ -510,9 +541,11 @@ __global__ __launch_bounds__(256, 2) void k_wscan_mma(WLib L, WWs ws, const uint
       // barrier so that a whole chunk of work covers their latency
       if (ch + 1 < NCH) {
 #pragma unroll
-        for (uint32_t st = 0; st < F::kSteps; ++st)
-          Ab[(ch + 1) & 1][st] =
-              *reinterpret_cast<const wv4i *>(abase + (ch + 1) * F::kChunkBytes + 32 * st);
+        for (int mq = 0; mq < QT; ++mq)
+#pragma unroll
+          for (uint32_t st = 0; st < F::kSteps; ++st)
+            Ab[(ch + 1) & 1][mq][st] = *reinterpret_cast<const wv4i *>(
+                abase[mq] + (ch + 1) * F::kChunkBytes + 32 * st);
       }
       const uint64_t wa = wr[ch][0], wb = wr[ch][1];
       mypop += (uint32_t)(__popcll(wa) + __popcll(wb));
@@ -534,16 +567,44 @@ __global__ __launch_bounds__(256, 2) void k_wscan_mma(WLib L, WWs ws, const uint
         }
       }
       __syncthreads();
-      if (live) {
-        const uint8_t *bbuf = bt[ch & 1];
+      // the wave's record rows 32 (CT rg + ct) + (lane & 31) of this chunk
+      const uint8_t *bbuf =
+          bt[ch & 1] + (32 * CT * rg + (lane & 31)) * RS + 16 * (lane >> 5);
+      if (live && FMT == 0) {
 #pragma unroll
         for (uint32_t st = 0; st < F::kSteps; ++st) {
 #pragma unroll
-          for (int ct = 0; ct < 4; ++ct) {
-            const wv4i bb = *reinterpret_cast<const wv4i *>(bbuf + (32 * ct + (lane & 31)) * RS +
-                                                             32 * st + 16 * (lane >> 5));
-            acc[ct] = F::mma(Ab[ch & 1][st], bb, acc[ct]);
+          for (int ct = 0; ct < CT; ++ct) {
+            const wv4i bb = *reinterpret_cast<const wv4i *>(bbuf + 32 * ct * RS + 32 * st);
+#pragma unroll
+            for (int mq = 0; mq < QT; ++mq)
+              acc[mq][ct] = F::mma(Ab[ch & 1][mq][st], bb, acc[mq][ct]);
           }
+        }
+      } else if (live) {
+        // fp4: the record fragments of step st + 1 are read from LDS while
+        // step st multiplies (two register sets; the scheduling barriers keep
+        // the compiler from sinking the reads next to their products, which
+        // left every product waiting for its read)
+        wv4i bq[2][CT];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+          bq[0][ct] = *reinterpret_cast<const wv4i *>(bbuf + 32 * ct * RS);
+#pragma unroll
+        for (uint32_t st = 0; st < F::kSteps; ++st) {
+          if (st + 1 < F::kSteps) {
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+              bq[(st + 1) & 1][ct] =
+                  *reinterpret_cast<const wv4i *>(bbuf + 32 * ct * RS + 32 * (st + 1));
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int mq = 0; mq < QT; ++mq)
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+              acc[mq][ct] = F::mma(Ab[ch & 1][mq][st], bq[st & 1][ct], acc[mq][ct]);
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
     }
@@ -553,23 +614,27 @@ __global__ __launch_bounds__(256, 2) void k_wscan_mma(WLib L, WWs ws, const uint
     // u = |q| - T - 1 + |r| - 2 q.r < 0 marks a candidate
     int32_t any = 0;
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct)
+    for (int mq = 0; mq < QT; ++mq)
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const uint32_t rw = 32 * wv + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-        const uint32_t col = 32 * ct + (lane & 31);
-        any |= cq[rw] + (int32_t)pr[col] - 2 * F::val(acc[ct], e);
-      }
+      for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const uint32_t rw = 32 * (QT * qg + mq) + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+          const uint32_t col = 32 * (CT * rg + ct) + (lane & 31);
+          any |= cq[rw] + (int32_t)pr[col] - 2 * F::val(acc[mq][ct], e);
+        }
     if (__ballot(any < 0) == 0) continue;
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-      const uint32_t col = 32 * ct + (lane & 31);
+    for (int mq = 0; mq < QT; ++mq)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const uint32_t col = 32 * (CT * rg + ct) + (lane & 31);
       const bool cok = v0 + col < vend;
       const uint64_t gc = cok ? wv2g(rs, v0 + col) : 0;
 #pragma unroll 1
       for (int e = 0; e < 16; ++e) {
-        const uint32_t rw = 32 * wv + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-        const int32_t dot = F::val(acc[ct], e);
+        const uint32_t rw = 32 * (QT * qg + mq) + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        const int32_t dot = F::val(acc[mq][ct], e);
         const int32_t u = cq[rw] + (int32_t)pr[col] - 2 * dot;
         const bool hit = u < 0 && cok && rw < qb.count;
         const uint64_t bal = __ballot(hit);
