@@ -111,16 +111,42 @@ __device__ __forceinline__ uint32_t cand_counts(const Workspace &ws, const Query
 }
 
 // Calls f(key) for every valid candidate; the block's threads share the work.
-// One segment: all threads stride over it.  Several: wave w takes segments
-// w, w + waves, ... (the spill area is segment nseg), four at a time so that
-// their loads are in flight together.
-template <class F>
+// One segment: all threads stride over it, four keys per thread at a time.
+// Several: wave w takes segments w, w + waves, ... (the spill area is segment
+// nseg), four at a time.  The four loads are issued without branches (a lane
+// with nothing to read reads slot 0, which every buffer of a query with
+// keff > 0 has), so that they are in flight together: under a branch each, the
+// compiler waited for every load before issuing the next.  Callers handle
+// keff == 0 before calling this.  DIST: only the distance (the key's high
+// word) is read and f gets it as (d << 32) -- half the bytes, and no load
+// whose unused low half the register allocator reuses (which made it wait for
+// the load).
+template <bool DIST = false, class F>
 __device__ __forceinline__ void cand_for_each(const Workspace &ws, const QueryInfo *qi,
                                               const uint32_t *m, F f) {
   const uint32_t nseg = qi->nseg, tid = threadIdx.x;
   const uint64_t *cand = ws.cand + qi->cand_off;
+  // slot i of the buffer: the whole key, or (DIST) its distance word
+  auto get = [&](uint64_t i) -> uint64_t {
+    if constexpr (DIST)
+      return (uint64_t)reinterpret_cast<const uint32_t *>(cand)[2 * i + 1] << 32;
+    else
+      return cand[i];
+  };
   if (nseg == 1) {
-    for (uint32_t i = tid; i < m[0]; i += blockDim.x) f(cand[i]);
+    const uint32_t n = m[0], nt = blockDim.x;
+    for (uint32_t i0 = tid; i0 < n; i0 += 4 * nt) {
+      uint64_t key[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t i = i0 + j * nt;
+        key[j] = get(i < n ? i : 0u);
+      }
+      __builtin_amdgcn_sched_barrier(0);  // all four loads go out first
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (i0 + j * nt < n) f(key[j]);
+    }
     return;
   }
   const uint32_t wv = tid >> 6, nw = blockDim.x >> 6, lane = tid & 63u;
@@ -132,15 +158,16 @@ __device__ __forceinline__ void cand_for_each(const Workspace &ws, const QueryIn
     for (int j = 0; j < 4; ++j) {
       const uint32_t s = s0 + j * nw;
       c[j] = s <= nseg ? m[s] : 0u;
-      if (lane < c[j]) key[j] = cand[(uint64_t)s * segcap + lane];
+      key[j] = get(lane < c[j] ? (uint64_t)s * segcap + lane : 0ull);
     }
+    __builtin_amdgcn_sched_barrier(0);  // all four loads go out first
 #pragma unroll
     for (int j = 0; j < 4; ++j)
       if (lane < c[j]) f(key[j]);
 #pragma unroll 1
     for (int j = 0; j < 4; ++j) {
-      const uint64_t *p = cand + (uint64_t)(s0 + j * nw) * segcap;
-      for (uint32_t i = lane + 64; i < c[j]; i += 64) f(p[i]);
+      const uint64_t p = (uint64_t)(s0 + j * nw) * segcap;
+      for (uint32_t i = lane + 64; i < c[j]; i += 64) f(get(p + i));
     }
   }
 }

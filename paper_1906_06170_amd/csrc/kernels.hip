@@ -136,11 +136,13 @@ __global__ __launch_bounds__(256) void k_bound(Lib lib, Workspace ws, uint32_t c
       for (uint64_t vb = a; vb < b; vb += 256 * 8) {
         Rec rec[8];
         bool ok[8];
+        // loads without branches (a lane past the range reads record a of
+        // it): under a branch each, the compiler waited between them
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const uint64_t v = vb + 256 * u + tid;
           ok[u] = v < b;
-          if (ok[u]) rec[u] = load_rec(lib, v + gofs);
+          rec[u] = load_rec(lib, (ok[u] ? v : a) + gofs);
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u)
@@ -226,7 +228,8 @@ __global__ __launch_bounds__(1024) void k_refine(Workspace ws) {
   for (uint32_t i = tid; i < kBins; i += blockDim.x) hist[i] = 0;
   cand_counts(ws, qi, m, &s_total, &s_over);
   if (s_over) return;
-  cand_for_each(ws, qi, m, [&](uint64_t key) { atomicAdd(&hist[(uint32_t)(key >> 32)], 1u); });
+  cand_for_each<true>(ws, qi, m,
+                      [&](uint64_t key) { atomicAdd(&hist[(uint32_t)(key >> 32)], 1u); });
   __syncthreads();
   if (tid < 64) {
     const int32_t T1 = (int32_t)ws.T[q];
