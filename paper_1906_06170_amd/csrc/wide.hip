@@ -78,7 +78,7 @@ struct WWs {
   const WBlock *qb;
   const uint64_t *item_off;  // per phase: nqb + 1 prefix of items
   const uint64_t *qw;        // q x W query words
-  uint8_t *qx;               // q x 64 W bytes: queries expanded for the matrix cores
+  uint8_t *qx;               // q x 64 W bytes: queries expanded for the int8 matrix cores
   uint32_t *T, *ctr, *flags, *count, *hist, *bdone;
   uint64_t *cand;
   fps_hit *out;
@@ -513,26 +513,34 @@ __global__ __launch_bounds__(256, 2) void k_wscan_mma(WLib L, WWs ws, const uint
       wr[ch][0] = rok ? x0 : 0ull;
       wr[ch][1] = rok ? x1 : 0ull;
     }
-    // the wave's query fragments of a chunk, read one chunk ahead (they come
-    // from L2: read when needed they stalled every chunk's products)
+    // The wave's query fragments of a chunk are read one chunk ahead (they
+    // come from L2: read when needed they stalled every chunk's products).
+    // int8 reads the expanded rows of qx; fp4 reads the raw query words and
+    // each lane expands its half of a word per K step (a quarter of the bytes
+    // read from L2: measured 2 % faster).
     const uint8_t *abase[QT];
+    const uint64_t *qraw[QT];
 #pragma unroll
-    for (int mq = 0; mq < QT; ++mq)
-      abase[mq] = ws.qx + (uint64_t)qid[32 * (QT * qg + mq) + (lane & 31)] * QROW +
-                  16 * (lane >> 5);
-    // two register sets named statically (the chunk loop is unrolled): chunk
-    // ch multiplies with Ab[ch & 1] while Ab[(ch + 1) & 1] is being loaded (a
+    for (int mq = 0; mq < QT; ++mq) {
+      const uint32_t qq = qid[32 * (QT * qg + mq) + (lane & 31)];
+      abase[mq] = ws.qx + (uint64_t)qq * QROW + 16 * (lane >> 5);
+      qraw[mq] = ws.qw + (uint64_t)qq * W;
+    }
+    // Two register sets named statically (the chunk loop is unrolled): chunk
+    // ch multiplies with set ch & 1 while set (ch + 1) & 1 is being loaded (a
     // copy from one set into the other made every chunk wait for the loads it
-    // had just issued)
-    // (every wave loads them, unconditionally: arow is a valid query row
-    // also for rows past the block, and loads under a branch made the
-    // compiler's wait counts assume the worst)
+    // had just issued).  Every wave loads them, unconditionally: rows past the
+    // block read query 0, and loads under a branch made the compiler's wait
+    // counts assume the worst.
     wv4i Ab[2][QT][F::kSteps];
+    uint64_t Aw[2][QT][F::kSteps];  // fp4: the raw words in flight
 #pragma unroll
     for (int mq = 0; mq < QT; ++mq)
 #pragma unroll
-      for (uint32_t st = 0; st < F::kSteps; ++st)
-        Ab[0][mq][st] = *reinterpret_cast<const wv4i *>(abase[mq] + 32 * st);
+      for (uint32_t st = 0; st < F::kSteps; ++st) {
+        if constexpr (FMT == 1) Aw[0][mq][st] = qraw[mq][st];
+        else Ab[0][mq][st] = *reinterpret_cast<const wv4i *>(abase[mq] + 32 * st);
+      }
     // Chunk ch is expanded into bt[ch & 1] while the other buffer may still be
     // read by the products of chunk ch - 1: one barrier per chunk.
 #pragma unroll
@@ -543,9 +551,22 @@ __global__ __launch_bounds__(256, 2) void k_wscan_mma(WLib L, WWs ws, const uint
 #pragma unroll
         for (int mq = 0; mq < QT; ++mq)
 #pragma unroll
-          for (uint32_t st = 0; st < F::kSteps; ++st)
-            Ab[(ch + 1) & 1][mq][st] = *reinterpret_cast<const wv4i *>(
-                abase[mq] + (ch + 1) * F::kChunkBytes + 32 * st);
+          for (uint32_t st = 0; st < F::kSteps; ++st) {
+            if constexpr (FMT == 1) Aw[(ch + 1) & 1][mq][st] = qraw[mq][kWChunk * (ch + 1) + st];
+            else
+              Ab[(ch + 1) & 1][mq][st] = *reinterpret_cast<const wv4i *>(
+                  abase[mq] + (ch + 1) * F::kChunkBytes + 32 * st);
+          }
+      }
+      if constexpr (FMT == 1) {
+#pragma unroll
+        for (int mq = 0; mq < QT; ++mq)
+#pragma unroll
+          for (uint32_t st = 0; st < F::kSteps; ++st) {
+            uint32_t o[8];
+            F::expand32((uint32_t)(Aw[ch & 1][mq][st] >> (32 * (lane >> 5))), o);
+            Ab[ch & 1][mq][st] = wv4i{(int)o[0], (int)o[1], (int)o[2], (int)o[3]};
+          }
       }
       const uint64_t wa = wr[ch][0], wb = wr[ch][1];
       mypop += (uint32_t)(__popcll(wa) + __popcll(wb));
@@ -1157,7 +1178,7 @@ static fps_status w_plan(const fps_wide *lib, uint32_t q, const uint32_t *k, con
   o = wal(o + 8ull * q * P->W);
   P->params = o;
   P->off_qx = o;
-  if (P->path == FPS_PATH_MFMA_I8 || P->path == FPS_PATH_MFMA_F4) o = wal(o + 8ull * P->W * 8 * q);
+  if (P->path == FPS_PATH_MFMA_I8) o = wal(o + 8ull * P->W * 8 * q);
   P->off_T = o;
   o = wal(o + 4ull * q);
   P->off_ctr = o;
@@ -1243,14 +1264,10 @@ static void w_launch_front(const WLib &L, const WWs &ws, const WPlan &P, hipStre
   const uint32_t chunks = (uint32_t)std::max<uint64_t>(1, (P.max_sample + chunk - 1) / chunk);
   hipLaunchKernelGGL((k_wbound<W>), dim3(chunks, (P.q + kWBoundQ - 1) / kWBoundQ), dim3(256), 0,
                      s, L, ws, (uint32_t)chunk, P.q);
-  if (P.path == FPS_PATH_MFMA_I8 || P.path == FPS_PATH_MFMA_F4) {
+  if (P.path == FPS_PATH_MFMA_I8) {  // (the fp4 kernel expands raw query words itself)
     const uint64_t parts = 2ull * W * P.q;
-    if (P.path == FPS_PATH_MFMA_I8)
-      hipLaunchKernelGGL((k_wexpand<W, 0>), dim3((uint32_t)((parts + 255) / 256)), dim3(256), 0, s,
-                         ws, P.q);
-    else
-      hipLaunchKernelGGL((k_wexpand<W, 1>), dim3((uint32_t)((parts + 255) / 256)), dim3(256), 0, s,
-                         ws, P.q);
+    hipLaunchKernelGGL((k_wexpand<W, 0>), dim3((uint32_t)((parts + 255) / 256)), dim3(256), 0, s,
+                       ws, P.q);
   }
 }
 
