@@ -434,8 +434,9 @@ __global__ __launch_bounds__(256, 2) void k_wscan_mma(WLib L, WWs ws, const uint
   constexpr uint32_t QROW = F::kChunkBytes * (W / kWChunk);  // bytes per expanded query
   constexpr uint32_t NCH = W / kWChunk;
   // A wave multiplies QT query tiles by CT record tiles of 32 x 32: 1 x 4.
-  // (2 x 2 halves the LDS reads per product but doubles the query fragments
-  // every wave reads from L2, and measured 1.5x slower.)
+  // (2 x 2 halves the LDS reads per product but doubles every wave's query
+  // fragments; measured 1.5x slower with expanded query rows from L2, and
+  // still 16 % slower with raw query words expanded in registers.)
   constexpr int QT = 1, CT = 4 / QT;
   __shared__ __attribute__((aligned(16))) uint8_t bt[2][kWMmaRT * RS];
   __shared__ int32_t cq[kWMmaQB];   // |q| - T - 1 (large for rows past the block)
