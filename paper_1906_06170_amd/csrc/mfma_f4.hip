@@ -28,6 +28,8 @@
 // d fragment, which holds bits 6, 7, 14, 15, ... of d (always zero), and the
 // bias digits in bytes 1..3 of dword 0 and byte 1 of dword 1 (bits 8..29 of d,
 // also zero).
+#include <type_traits>
+
 #include "f4_digits.h"
 #include "mfma_common.h"
 
@@ -190,12 +192,15 @@ __device__ __forceinline__ void decode_f4(const Workspace &ws, const Stage &st, 
   static_assert(kE <= 64, "one bit per result element");
   const uint32_t g = (uint32_t)(st.g0 + 32 * c + (lane & 31));
   const uint32_t rowh = 4 * (lane >> 5);
-  uint64_t m = 0;
+  // the sign bits of the elements (every sum starts from +0, so an exact
+  // zero is +0: a set sign bit is a negative product)
+  typedef std::conditional_t<(kE <= 32), uint32_t, uint64_t> Mask;
+  Mask m = 0;
 #pragma unroll
   for (int mq = 0; mq < MQ; ++mq)
 #pragma unroll
     for (int e = 0; e < 16; ++e)
-      m |= (uint64_t)(acc[mq][e] < 0.0f ? 1u : 0u) << (16 * mq + e);
+      m |= (Mask)(__float_as_uint(acc[mq][e]) >> 31) << (16 * mq + e);
   for (;;) {
     const bool has = m != 0;
     const uint64_t bal = __ballot(has);
